@@ -1,0 +1,253 @@
+/*
+ * wpm.h - C ABI of the MI355X weak-pseudo-manifold sweep engine.
+ *
+ * The engine implements the enumeration of Choi, Jang and Vallee,
+ * "The characterization of (n-1)-spheres with n+4 vertices having maximal
+ * Buchstaber number" (arXiv 2301.00806):
+ *   input  a set F of candidate facets (n-subsets of [m]) and the properties
+ *          G (here: the upper-bound property of Section 4.2);
+ *   output every weak pseudo-manifold K with facets in F satisfying G
+ *          (problem statement of Section 2.1).
+ * A complex K with facets in F is a 0/1 vector of length M = |F|; it is a weak
+ * pseudo-manifold iff every entry of A K lies in {0, 2}, where A is the
+ * ridge-facet incidence matrix (Proposition 2.1).  Such vectors lie in the F2
+ * kernel of A, so the engine sweeps all 2^k combinations of a kernel basis
+ * (Section 2.1) on the GPU and keeps the ones that pass the check.
+ *
+ * Conventions
+ *   - Vertices are 0..m-1 (the paper uses 1..m); a vertex set is a uint32
+ *     mask, bit v = vertex v.  m <= 32.
+ *   - lambda[i] is column i of the n x m mod-2 characteristic matrix, bit t =
+ *     row t (Section 3.1, characteristic maps).
+ *   - Facets and ridges are listed in lexicographic order of their sorted
+ *     vertex tuples.
+ *   - A facet bit vector of length M is stored in W = ceil(M/32) uint32
+ *     words, bit j of word j/32 = facet j.
+ *   - A kernel coordinate vector x (bit t = coefficient of basis vector t) is
+ *     a uint64; the complex is K = sum_t x_t K_t over F2.
+ *   - The empty complex (x = 0) is not reported: it is not an
+ *     (n-1)-dimensional pure complex.  Every count covers nonzero x only.
+ *
+ * Errors: every call returns WPM_OK (0) or a negative status; nothing aborts
+ * or throws.  Capacity errors report the size needed in the *_out/needed
+ * argument and leave every count exact.  Calls keep no global state except a
+ * thread-local copy of the last HIP error (wpm_last_hip_error).  Host calls
+ * are reentrant; device calls are ordered on the stream passed in.
+ *
+ * Ownership: the caller owns every buffer, host and device.  Device buffers
+ * are plain device pointers (for example torch.empty(..., device="cuda")
+ * .data_ptr()); `stream` is a hipStream_t passed as void*.  wpm_enumerate
+ * makes no device allocation.
+ */
+#ifndef WPM_H
+#define WPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    WPM_OK = 0,
+    WPM_EINVAL = -1, /* invalid argument or malformed input */
+    WPM_ECAP = -2,   /* a caller buffer is too small; the size needed is reported */
+    WPM_EKMAX = -3,  /* kernel dimension above WPM_MAX_K */
+    WPM_EHIP = -4,   /* HIP runtime error; see wpm_last_hip_error() */
+    WPM_ELIMIT = -5  /* instance outside the engine's table limits (WPM_MAX_*) */
+};
+
+#define WPM_MAX_K 64        /* kernel dimension (x is a uint64) */
+#define WPM_MAX_M 1024      /* candidate facets per instance (W <= 32 words) */
+#define WPM_MAX_GROUPS 16   /* 32-ridge groups of critical ridges (<= 512 ridges) */
+#define WPM_MAX_SLOTS 8     /* parents-1 of a critical ridge */
+#define WPM_LOW_BITS 6      /* Gray steps unrolled per block: 2^6 */
+#define WPM_TABLE_ROWS 128  /* low-part rows staged per instance: 2 * 2^6 */
+
+/* Human-readable text of a status code (static storage). */
+const char *wpm_strerror(int status);
+
+/* Text of the last HIP error seen by this thread (static storage). */
+const char *wpm_last_hip_error(void);
+
+/*
+ * Candidate facets F(lambda) (Section 4.2): the n-subsets S of [m] whose
+ * columns {lambda(i) : i in S} form a basis of F2^n, i.e. the facets of the
+ * binary matroid of lambda.  A mod-2 characteristic map over K exists with
+ * matrix lambda iff K is a subcomplex of that matroid (Proposition 4.2 and
+ * the paragraph before it), so these are the only facets a complex
+ * supporting lambda can use.
+ *   n, m       1 <= n <= m <= 32, n <= 20
+ *   lambda     [m] host array, column i as an n-bit integer (< 2^n)
+ *   facets     [cap] host array; receives vertex masks in lexicographic order
+ *   M_out      receives |F(lambda)|; if it exceeds cap, WPM_ECAP
+ */
+int wpm_build_candidates(int n, int m, const uint32_t *lambda, uint32_t *facets, int32_t cap,
+                         int32_t *M_out);
+
+/*
+ * Ridges and an F2 basis of the kernel of the ridge-facet incidence matrix
+ * A(F) (Section 2.1: a_ij = 1 iff ridge r_i lies in facet F_j; weak
+ * pseudo-manifolds lie in ker_F2 A; any basis reaches each of them as exactly
+ * one combination).
+ *   n, m       2 <= n <= m <= 32
+ *   facets     [M] host array of distinct n-element vertex masks below 2^m
+ *   ridges     [cap_r] host array; receives the (n-1)-subsets of the facets in
+ *              lexicographic order; *N_out = their number
+ *   basis      [cap_k * W] host array; receives basis vector t as W words at
+ *              basis + t*W (bit j of word j/32 = facet j); *k_out = k
+ *   The basis is the reduced-echelon null-space basis: vector t has a 1 at
+ *   the t-th non-pivot facet and 0 at the other non-pivot facets.
+ * Returns WPM_ECAP if N > cap_r or k > cap_k (sizes still reported),
+ * WPM_EKMAX is not returned here (k may exceed 64; wpm_pack_instance rejects).
+ */
+int wpm_kernel_basis(int n, int m, const uint32_t *facets, int32_t M, uint32_t *ridges,
+                     int32_t cap_r, int32_t *N_out, uint32_t *basis, int32_t cap_k,
+                     int32_t *k_out);
+
+/* Upper bound of Section 4.2: facet count of the cyclic polytope C^n(n+4),
+ * C(n+4-ceil(n/2), 4) + C(n+3-floor(n/2), 4).  g(K) > 0 iff |K| <= it. */
+int64_t wpm_ubt_bound(int n);
+
+/* Summary of a packed instance. */
+typedef struct wpm_instance_info {
+    int32_t n, m, M, N, k;
+    int32_t W;            /* facet words */
+    int32_t n_crit;       /* ridges with >= 4 parents (only these can fail) */
+    int32_t groups;       /* 32-ridge groups, group 0 = the fast filter */
+    int32_t slots;        /* slot words per ridge in groups >= 1 */
+    int32_t n_filter;     /* ridges in the fast filter group */
+    int32_t row_words;    /* words per basis row of the packed table */
+    int32_t max_facets;   /* upper bound applied (0 = none) */
+    int64_t table_words;  /* size of the packed table in uint32 words */
+    double filter_pass;   /* estimated fraction of x passing the filter */
+    double full_pass;     /* estimated fraction of x passing every ridge */
+    float features[16];   /* cost-model features (see wpm_cost_features) */
+} wpm_instance_info;
+
+/*
+ * Pack one instance for the GPU sweep: selects the fast-filter ridges and lays
+ * out the bit-sliced ridge-slot rows and facet rows of every basis vector.
+ *   facets[M], basis[k*W]  as returned by the two calls above
+ *   max_facets             bound on |K| (0 = none; the paper applies
+ *                          wpm_ubt_bound(n) when m = n + 4, Algorithm 4.4)
+ *   seed                   seeds the sampling that ranks ridges (any value;
+ *                          never changes results)
+ *   table, cap_words       host output; with table == NULL or a too small
+ *                          cap the call returns WPM_ECAP after filling info
+ * Returns WPM_EKMAX if k > 64, WPM_ELIMIT if M, the critical ridge count or a
+ * ridge's parent count exceeds the WPM_MAX_* limits.
+ */
+int wpm_pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
+                      int32_t k, int32_t max_facets, uint64_t seed, uint32_t *table,
+                      int64_t cap_words, wpm_instance_info *info);
+
+/* ------------------------------------------------------------ scheduling */
+
+/* One unit of GPU work: lanes 0..lanes-1 of a workgroup sweep the Gray index
+ * ranges [(first + l) * 2^cbits, (first + l + 1) * 2^cbits) of one instance. */
+typedef struct wpm_item {
+    uint32_t instance;
+    uint16_t cbits;   /* per-lane chunk: 2^cbits consecutive Gray indices, >= 7 */
+    uint16_t lanes;   /* lanes used, 1..workgroup size */
+    uint64_t first;   /* first lane chunk */
+} wpm_item;
+
+enum {
+    WPM_SCHED_PLAIN = 0,   /* one launch per instance over its own items */
+    WPM_SCHED_STATIC = 1,  /* one persistent launch, workgroup g takes items g, g+G, ... */
+    WPM_SCHED_DYNAMIC = 2  /* one persistent launch, items popped from a device queue */
+};
+
+/*
+ * Split instances into items.
+ *   k[num]           kernel dimension of each instance
+ *   cost[num]        relative cost per vector (NULL = 1.0 for all); an item's
+ *                    cost is cost[i] * vectors in the item
+ *   cbits            lane chunk bits (clamped to [7, max(k,7)] per instance)
+ *   lanes            lanes per item (workgroup size)
+ *   max_items_per_instance  > 0: coarsen chunks so an instance yields at most
+ *                    this many items (raises cbits)
+ *   order            0 = instance order, 1 = descending item cost (LPT)
+ *   items, cap       output (host); *n_out = item count (WPM_ECAP if > cap)
+ */
+int wpm_build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits,
+                    int32_t lanes, int32_t max_items_per_instance, int32_t order,
+                    wpm_item *items, int64_t cap, int64_t *n_out);
+
+/* Device-resident batch. */
+typedef struct wpm_batch {
+    int32_t num_instances;
+    int32_t max_row_words;     /* max info.row_words over the batch (LDS sizing) */
+    int32_t max_groups;        /* max info.groups */
+    int32_t max_slots;         /* max info.slots (4 or 8) */
+    int32_t max_words;         /* max info.W */
+    int32_t reserved;
+    const uint32_t *d_tables;  /* device: packed tables, concatenated (16-byte aligned each) */
+    const int64_t *d_offsets;  /* device: word offset of each table in d_tables */
+} wpm_batch;
+
+typedef struct wpm_sched {
+    int32_t mode;              /* WPM_SCHED_* */
+    int32_t wg_size;           /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+    int32_t grid;              /* persistent modes: workgroups (0 = 4 per CU) */
+    int32_t reserved;
+    const wpm_item *d_items;   /* device: the items */
+    const wpm_item *h_items;   /* host copy (PLAIN mode launches per instance from it) */
+    int64_t num_items;
+    uint32_t *d_scratch;       /* device: >= 4 words (queue head), cleared by the call */
+    uint64_t *d_item_times;    /* optional device [num_items][2]: start, end (s_memrealtime) */
+} wpm_sched;
+
+/*
+ * Sweep every item on `stream`.
+ *   d_survivors [cap][2] uint64 device records {x, instance}; only the first
+ *               cap survivors are written, in no particular order
+ *   d_counts    [num_instances] uint64 device; set to each instance's exact
+ *               number of results (cleared by the call)
+ *   d_total     [1] uint64 device; total results (> cap: the caller needs a
+ *               larger buffer; wpm_collect returns WPM_ECAP)
+ *   d_stats     optional [8] uint64 device counters: [0] filter fires (wave
+ *               steps with a lane passing the fast filter), [1] lanes passing
+ *               every ridge check, [2] vectors rejected by the upper bound
+ * Asynchronous: returns after enqueueing.  Items must describe chunks inside
+ * each instance's 2^max(k,7) Gray range (checked on the host for PLAIN mode
+ * and by wpm_build_queue's construction otherwise).
+ */
+int wpm_enumerate(const wpm_batch *batch, const wpm_sched *sched, uint64_t *d_survivors,
+                  uint64_t cap, uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats,
+                  void *stream);
+
+/* Device facts the scheduler needs: compute units, the s_memrealtime clock
+ * rate (kHz, the unit of d_item_times) and the LDS limit per workgroup. */
+int wpm_device_query(int32_t *num_cus, int64_t *wallclock_khz, int32_t *lds_per_block);
+
+/* Host view of an instance for wpm_collect. */
+typedef struct wpm_host_instance {
+    int32_t M, k;
+    const uint32_t *facets; /* [M] */
+    const uint32_t *basis;  /* [k * ceil(M/32)] */
+} wpm_host_instance;
+
+/*
+ * Synchronise `stream`, copy counts and survivors to the host and expand each
+ * survivor x into its facet list K = sum_t x_t K_t.
+ *   h_counts     [num] receives the exact per-instance counts
+ *   h_out        [out_cap] uint32; per instance, in canonical order, each
+ *                result as [len, facet masks ascending]; results of one
+ *                instance are sorted lexicographically
+ *   h_offsets    [num + 1] int64: word offset of each instance's results
+ *   out_words    receives the words needed
+ * Returns WPM_ECAP if the survivor buffer overflowed (*total > cap) or
+ * out_cap is too small.
+ */
+int wpm_collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_survivors,
+                uint64_t cap, const uint64_t *d_counts, const uint64_t *d_total,
+                uint64_t *h_counts, uint32_t *h_out, int64_t out_cap, int64_t *out_words,
+                int64_t *h_offsets, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WPM_H */

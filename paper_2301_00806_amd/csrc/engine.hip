@@ -1,0 +1,228 @@
+// Device side of the ABI: launches of the sweep and collection of results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+#include "launch.h"
+
+namespace wpm {
+
+namespace {
+thread_local char g_hip_err[256] = "no HIP error";
+
+__global__ void zero_u64(unsigned long long *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+int hip_fail(const char *what, hipError_t e) {
+    set_hip_error(what, (int)e, hipGetErrorString(e));
+    return WPM_EHIP;
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return hip_fail(#expr, _e); \
+    } while (0)
+
+int zero(void *p, int64_t n, hipStream_t st) {
+    if (!p || n <= 0) return WPM_OK;
+    const int bs = 256;
+    const int64_t nb = (n + bs - 1) / bs;
+    hipLaunchKernelGGL(zero_u64, dim3((unsigned)nb), dim3(bs), 0, st, (unsigned long long *)p, n);
+    HIP_TRY(hipGetLastError());
+    return WPM_OK;
+}
+
+int pick_gm(int g) { return g <= 2 ? 2 : g <= 4 ? 4 : g <= 8 ? 8 : 16; }
+int pick_wm(int w) { return w <= 4 ? 4 : w <= 16 ? 16 : 32; }
+
+hipError_t launch(int gm, int qs, int wm, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                  const uint32_t *tables, const int64_t *offsets, const wpm_item *items,
+                  const KArgs &a) {
+    switch (gm) {
+        case 2: return launch_sweep_g2(qs, wm, grid, block, lds, st, tables, offsets, items, a);
+        case 4: return launch_sweep_g4(qs, wm, grid, block, lds, st, tables, offsets, items, a);
+        case 8: return launch_sweep_g8(qs, wm, grid, block, lds, st, tables, offsets, items, a);
+        default: return launch_sweep_g16(qs, wm, grid, block, lds, st, tables, offsets, items, a);
+    }
+}
+
+hipError_t occupancy(int gm, int qs, int wm, int *nb, int block, size_t lds) {
+    switch (gm) {
+        case 2: return occupancy_sweep_g2(qs, wm, nb, block, lds);
+        case 4: return occupancy_sweep_g4(qs, wm, nb, block, lds);
+        case 8: return occupancy_sweep_g8(qs, wm, nb, block, lds);
+        default: return occupancy_sweep_g16(qs, wm, nb, block, lds);
+    }
+}
+}  // namespace
+
+void set_hip_error(const char *what, int code, const char *text) {
+    std::snprintf(g_hip_err, sizeof(g_hip_err), "%s: %d (%s)", what, code, text ? text : "?");
+}
+
+const char *last_hip_error() { return g_hip_err; }
+
+int device_query(int32_t *num_cus, int64_t *wallclock_khz, int32_t *lds_per_block) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int v = 0;
+    if (num_cus) {
+        HIP_TRY(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev));
+        *num_cus = v;
+    }
+    if (wallclock_khz) {
+        HIP_TRY(hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev));
+        *wallclock_khz = v;
+    }
+    if (lds_per_block) {
+        HIP_TRY(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        *lds_per_block = v;
+    }
+    return WPM_OK;
+}
+
+int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t cap,
+              uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats, void *stream) {
+    if (!b || !s || !d_counts || !d_total || (cap > 0 && !d_surv)) return WPM_EINVAL;
+    if (b->num_instances < 0 || !b->d_tables || !b->d_offsets) return WPM_EINVAL;
+    if (b->max_groups < 1 || b->max_groups > WPM_MAX_GROUPS) return WPM_EINVAL;
+    if (b->max_slots != 4 && b->max_slots != 8) return WPM_EINVAL;
+    if (b->max_words < 0 || b->max_words > 32 || b->max_row_words < 4) return WPM_EINVAL;
+    if (s->wg_size < 64 || s->wg_size > 1024 || (s->wg_size % 64)) return WPM_EINVAL;
+    if (s->num_items < 0 || (s->num_items > 0 && !s->d_items)) return WPM_EINVAL;
+    if (s->mode < WPM_SCHED_PLAIN || s->mode > WPM_SCHED_DYNAMIC) return WPM_EINVAL;
+    if (s->mode == WPM_SCHED_PLAIN && s->num_items > 0 && !s->h_items) return WPM_EINVAL;
+    if (s->mode == WPM_SCHED_DYNAMIC && !s->d_scratch) return WPM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int gm = pick_gm(b->max_groups), qs = b->max_slots, wm = pick_wm(b->max_words);
+    const size_t lds = (size_t)WPM_TABLE_ROWS * (size_t)b->max_row_words * sizeof(uint32_t);
+    int32_t lds_max = 0;
+    int rc = device_query(nullptr, nullptr, &lds_max);
+    if (rc) return rc;
+    if (lds > (size_t)lds_max) return WPM_ELIMIT;
+
+    int st_rc;
+    if ((st_rc = zero(d_counts, b->num_instances, st))) return st_rc;
+    if ((st_rc = zero(d_total, 1, st))) return st_rc;
+    if ((st_rc = zero(d_stats, 8, st))) return st_rc;
+    if (s->d_scratch && (st_rc = zero(s->d_scratch, 2, st))) return st_rc;
+    if (s->num_items == 0) return WPM_OK;
+
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.num_items = s->num_items;
+    a.head = (unsigned long long *)s->d_scratch;
+    a.surv = d_surv;
+    a.cap = cap;
+    a.counts = (unsigned long long *)d_counts;
+    a.total = (unsigned long long *)d_total;
+    a.stats = (unsigned long long *)d_stats;
+    a.times = s->d_item_times;
+    const dim3 block((unsigned)s->wg_size);
+    if (s->mode == WPM_SCHED_PLAIN) {
+        // One launch per instance: a grid of exactly that instance's items.
+        a.mode = 0;
+        int64_t i = 0;
+        while (i < s->num_items) {
+            int64_t e = i;
+            while (e < s->num_items && s->h_items[e].instance == s->h_items[i].instance) ++e;
+            if ((int)s->h_items[i].instance >= b->num_instances) return WPM_EINVAL;
+            a.item_base = i;
+            a.num_items = e;
+            const int64_t nb = e - i;
+            HIP_TRY(launch(gm, qs, wm, dim3((unsigned)nb), block, lds, st, b->d_tables, b->d_offsets,
+                           s->d_items, a));
+            i = e;
+        }
+        return WPM_OK;
+    }
+    int grid = s->grid;
+    if (grid <= 0) {
+        int32_t cus = 0;
+        if ((rc = device_query(&cus, nullptr, nullptr))) return rc;
+        int nb = 0;
+        HIP_TRY(occupancy(gm, qs, wm, &nb, s->wg_size, lds));
+        grid = std::max(1, nb) * cus;
+    }
+    a.mode = (s->mode == WPM_SCHED_STATIC) ? 1 : 2;
+    HIP_TRY(launch(gm, qs, wm, dim3((unsigned)grid), block, lds, st, b->d_tables, b->d_offsets,
+                   s->d_items, a));
+    return WPM_OK;
+}
+
+int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv, uint64_t cap,
+            const uint64_t *d_counts, const uint64_t *d_total, uint64_t *h_counts, uint32_t *h_out,
+            int64_t out_cap, int64_t *out_words, int64_t *h_offsets, void *stream) {
+    if (num < 0 || !d_counts || !d_total || !h_counts || !out_words || !h_offsets ||
+        (num > 0 && !insts))
+        return WPM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    uint64_t total = 0;
+    HIP_TRY(hipMemcpyAsync(h_counts, d_counts, sizeof(uint64_t) * (size_t)num, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&total, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const uint64_t got = std::min(total, cap);
+    std::vector<uint64_t> rec(2 * got);
+    if (got) {
+        HIP_TRY(hipMemcpyAsync(rec.data(), d_surv, sizeof(uint64_t) * 2 * got, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    uint64_t sum = 0;
+    for (int i = 0; i < num; ++i) sum += h_counts[i];
+    if (total > cap) {
+        *out_words = -1;
+        return WPM_ECAP;
+    }
+    if (sum != total) return WPM_EINVAL;  // counts and records disagree: corrupted buffers
+    // group by instance, expand x -> facet list, canonical order
+    std::vector<std::vector<uint64_t>> per(num);
+    for (uint64_t r = 0; r < got; ++r) {
+        const uint64_t inst = rec[2 * r + 1];
+        if (inst >= (uint64_t)num) return WPM_EINVAL;
+        per[inst].push_back(rec[2 * r]);
+    }
+    int64_t words = 0;
+    std::vector<std::vector<std::vector<uint32_t>>> res(num);
+    for (int i = 0; i < num; ++i) {
+        const int M = insts[i].M, W = (M + 31) / 32, k = insts[i].k;
+        auto &ri = res[i];
+        ri.reserve(per[i].size());
+        std::vector<uint32_t> K(W);
+        for (uint64_t x : per[i]) {
+            if (k < 64 && (x >> k)) return WPM_EINVAL;
+            std::fill(K.begin(), K.end(), 0u);
+            for (uint64_t b = x; b; b &= b - 1) {
+                const int t = __builtin_ctzll(b);
+                for (int w = 0; w < W; ++w) K[w] ^= insts[i].basis[(size_t)t * W + w];
+            }
+            std::vector<uint32_t> f;
+            for (int w = 0; w < W; ++w)
+                for (uint32_t v = K[w]; v; v &= v - 1) f.push_back(insts[i].facets[w * 32 + __builtin_ctz(v)]);
+            std::sort(f.begin(), f.end());
+            words += 1 + (int64_t)f.size();
+            ri.push_back(std::move(f));
+        }
+        std::sort(ri.begin(), ri.end());
+    }
+    *out_words = words;
+    if (!h_out || out_cap < words) return WPM_ECAP;
+    int64_t w = 0;
+    for (int i = 0; i < num; ++i) {
+        h_offsets[i] = w;
+        for (auto &f : res[i]) {
+            h_out[w++] = (uint32_t)f.size();
+            for (uint32_t v : f) h_out[w++] = v;
+        }
+    }
+    h_offsets[num] = w;
+    return WPM_OK;
+}
+
+}  // namespace wpm

@@ -1,0 +1,98 @@
+// Work decomposition for the sweep and the cost-model features.
+//
+// The 2^kp Gray indices of an instance are cut into lane chunks of 2^c
+// consecutive indices (c >= 7, so each lane walks whole 64-step blocks and
+// every lane of a workgroup flips the same basis vector at the same step).
+// An item hands `lanes` consecutive chunks to the lanes of one workgroup.
+// Chunks are independent: any split or order of items gives the same counts.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+
+namespace wpm {
+
+int build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits, int32_t lanes,
+                int32_t max_items_per_instance, int32_t order, wpm_item *items, int64_t cap,
+                int64_t *n_out) {
+    if (!k || !n_out || num < 0 || lanes < 1 || lanes > 1024 || cbits < 0 || order < 0 ||
+        order > 1)
+        return WPM_EINVAL;
+    struct Tmp {
+        wpm_item it;
+        double cost;
+    };
+    std::vector<Tmp> out;
+    int64_t total = 0;
+    for (int i = 0; i < num; ++i) {
+        if (k[i] < 0 || k[i] > WPM_MAX_K) return WPM_EINVAL;
+        const int kp = std::max(k[i], 7);
+        int c = std::min(std::max(cbits, 7), kp);
+        auto n_items = [&](int cc) -> uint64_t {
+            const int cb = kp - cc;  // log2 of the chunk count
+            if (cb >= 62) return ~0ull >> 1;
+            const uint64_t chunks = 1ull << cb;
+            return (chunks + lanes - 1) / lanes;
+        };
+        if (max_items_per_instance > 0)
+            while (c < kp && n_items(c) > (uint64_t)max_items_per_instance) ++c;
+        const uint64_t ni = n_items(c);
+        if (ni > (uint64_t)(INT64_MAX / 4)) return WPM_ELIMIT;
+        total += (int64_t)ni;
+        if (total > cap || !items) continue;
+        const uint64_t chunks = 1ull << (kp - c);
+        const double cv = cost ? (double)cost[i] : 1.0;
+        for (uint64_t q = 0; q < ni; ++q) {
+            Tmp t;
+            t.it.instance = (uint32_t)i;
+            t.it.cbits = (uint16_t)c;
+            const uint64_t first = q * (uint64_t)lanes;
+            t.it.lanes = (uint16_t)std::min<uint64_t>((uint64_t)lanes, chunks - first);
+            t.it.first = first;
+            t.cost = cv * (double)t.it.lanes * std::ldexp(1.0, c);
+            out.push_back(t);
+        }
+    }
+    *n_out = total;
+    if (total > cap || !items) return WPM_ECAP;
+    if (order == 1)
+        std::stable_sort(out.begin(), out.end(),
+                         [](const Tmp &a, const Tmp &b) { return a.cost > b.cost; });
+    for (size_t i = 0; i < out.size(); ++i) items[i] = out[i].it;
+    return WPM_OK;
+}
+
+// Sixteen per-instance features for the cost model, all cheap to compute
+// before any sweep:
+//   0 n   1 m   2 k   3 log2 M   4 log2 N   5 critical ridges / 32   6 W
+//   7 log2(max_facets + 1)   8..12 fraction of ridges with 1, 2, 3, 4, >=5
+//   parents   13 groups   14 log10 estimated fast-filter pass rate
+//   15 log10 estimated full-check pass rate (both from the packing samples)
+void cost_features(const wpm_instance_info &info, const Incidence &inc,
+                   const std::vector<int32_t> &crit, float *out) {
+    std::memset(out, 0, sizeof(float) * 16);
+    out[0] = (float)info.n;
+    out[1] = (float)info.m;
+    out[2] = (float)info.k;
+    out[3] = (float)std::log2(std::max(1, info.M));
+    out[4] = (float)std::log2(std::max(1, inc.N));
+    out[5] = (float)crit.size() / 32.0f;
+    out[6] = (float)info.W;
+    out[7] = (float)std::log2((double)info.max_facets + 1.0);
+    if (inc.N > 0) {
+        int h[5] = {0, 0, 0, 0, 0};
+        for (int r = 0; r < inc.N; ++r) {
+            const int p = inc.parent_off[r + 1] - inc.parent_off[r];
+            h[std::min(std::max(p, 1), 5) - 1]++;
+        }
+        for (int i = 0; i < 5; ++i) out[8 + i] = (float)h[i] / (float)inc.N;
+    }
+    out[13] = (float)info.groups;
+    out[14] = (float)std::log10(std::max(info.filter_pass, 1e-9));
+    out[15] = (float)std::log10(std::max(info.full_pass, 1e-9));
+}
+
+}  // namespace wpm

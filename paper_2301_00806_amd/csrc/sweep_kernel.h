@@ -1,0 +1,293 @@
+// The Gray-code sweep of the F2 kernel on gfx950 (device code).
+//
+// Every lane owns a chunk of 2^c consecutive Gray indices i of one instance
+// and visits x = i ^ (i >> 1), so consecutive vectors differ in the single
+// basis vector t = ctz(i + 1) and K changes by XOR with that basis row
+// (Section 2.1: the weak pseudo-manifolds are among the 2^k combinations of a
+// kernel basis).  Chunks are 2^c-aligned with c >= 7, so all lanes of a
+// workgroup flip the same t at the same step: the XOR operands are
+// wave-uniform and live in SGPRs.
+//
+// A step checks the ridges whose parents Proposition 2.1 constrains, in the
+// bit-sliced slot form built by the packer (a ridge fails iff at least 3 of
+// its first p-1 parent bits are set).  Work is split in two phases per block
+// of 64 steps:
+//   phase 1  the fast filter: 32 ridges in 4 slot words held in VGPRs,
+//            updated by 4 XORs and tested by 3 bit-logic ops per step;
+//            the steps where some lane passes are recorded in a 64-bit mask.
+//   phase 2  for each recorded step only: the lane's state is rebuilt as
+//            P ^ T[step], where P (per lane, VGPRs) is the contribution of
+//            the basis vectors above bit 6 and T (LDS, 128 rows staged per
+//            instance) the contribution of the low 6 bits; the remaining ridge
+//            groups are checked with wave-uniform early exit, then the
+//            facet count |K| (the upper-bound property of Section 4.2) and
+//            x != 0.  Survivors are compacted with a wave ballot and prefix
+//            count into one atomic slot reservation per wave.
+// Dot products and parities reduce to AND, XOR and popcount on bit masks, as
+// in Section 2.3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/wpm.h"
+
+namespace wpm {
+
+constexpr int DEV_HDR_WORDS = 16;  // must match the host packer's header size
+enum {
+    D_K = 1, D_KP = 2, D_M = 3, D_W = 4, D_G = 5, D_QS = 6, D_RS = 7, D_MAXF = 8
+};
+
+struct KArgs {
+    int64_t num_items;
+    int64_t item_base;
+    unsigned long long *head;
+    uint64_t *surv;
+    uint64_t cap;
+    unsigned long long *counts;
+    unsigned long long *total;
+    unsigned long long *stats;
+    uint64_t *times;
+    int mode;  // 0 direct (one item per workgroup), 1 static stride, 2 dynamic queue
+    int pad;
+};
+
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+}
+__device__ __forceinline__ uint32_t and3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x80);
+}
+// Per ridge bit: at least 3 of the 4 slot words set.
+__device__ __forceinline__ uint32_t fail4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    return (d & maj3(a, b, c)) | and3(a, b, c);
+}
+
+template <int QS>
+__device__ __forceinline__ uint32_t fail_slots(const uint32_t *s) {
+    if constexpr (QS == 4) {
+        return fail4(s[0], s[1], s[2], s[3]);
+    } else {
+        uint32_t c1 = s[0], c2 = 0, c3 = 0;
+#pragma unroll
+        for (int q = 1; q < QS; ++q) {
+            c3 |= c2 & s[q];
+            c2 |= c1 & s[q];
+            c1 |= s[q];
+        }
+        return c3;
+    }
+}
+
+template <int GM, int QS, int WM>
+struct Layout {
+    static constexpr int KR = 4 + (GM - 1) * QS;  // register index of the facet words
+    static constexpr int PW = KR + WM;
+};
+
+// P ^= row & msk over the words an instance uses.  Registers use the
+// template stride QS; the row uses the instance's own stride mqs (<= QS).
+template <int GM, int QS, int WM>
+__device__ __forceinline__ void xor_row(uint32_t *P, const uint32_t *row, uint32_t msk, int G,
+                                        int W, int mqs) {
+    constexpr int KR = Layout<GM, QS, WM>::KR;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) P[q] ^= row[q] & msk;
+#pragma unroll
+    for (int g = 1; g < GM; ++g) {
+        if (g < G) {
+#pragma unroll
+            for (int q = 0; q < QS; ++q)
+                if (QS == 4 || q < mqs) P[4 + (g - 1) * QS + q] ^= row[4 + (g - 1) * mqs + q] & msk;
+        }
+    }
+    const int koff = 4 + (G - 1) * mqs;
+#pragma unroll
+    for (int w = 0; w < WM; ++w)
+        if (w < W) P[KR + w] ^= row[koff + w] & msk;
+}
+
+__device__ __forceinline__ uint64_t rfl64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int GM, int QS, int WM>
+__global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__ tables,
+                                                     const int64_t *__restrict__ offsets,
+                                                     const wpm_item *__restrict__ items, KArgs a) {
+    extern __shared__ uint32_t lds_T[];  // [128][RS]
+    __shared__ unsigned long long s_item;
+    constexpr int KR = Layout<GM, QS, WM>::KR;
+    constexpr int PW = Layout<GM, QS, WM>::PW;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    int64_t staged = -1;
+    uint32_t n_fire = 0, n_ridge = 0, n_ubt = 0;  // wave-uniform statistics
+
+    for (int64_t round = 0;; ++round) {
+        int64_t it;
+        if (a.mode == 0) {
+            if (round > 0) break;
+            it = a.item_base + (int64_t)blockIdx.x;
+        } else if (a.mode == 1) {
+            it = (int64_t)blockIdx.x + round * (int64_t)gridDim.x;
+        } else {
+            if (tid == 0) s_item = atomicAdd(a.head, 1ull);
+            __syncthreads();
+            it = (int64_t)s_item;
+        }
+        if (it >= a.num_items) break;
+        uint64_t t_start = 0;
+        if (tid == 0 && a.times) t_start = __builtin_amdgcn_s_memrealtime();
+
+        const wpm_item itm = items[it];
+        const uint32_t inst = __builtin_amdgcn_readfirstlane(itm.instance);
+        const int c = __builtin_amdgcn_readfirstlane((uint32_t)itm.cbits);
+        const int lanes = __builtin_amdgcn_readfirstlane((uint32_t)itm.lanes);
+        const uint64_t first = rfl64(itm.first);
+        const uint32_t *__restrict__ tab = tables + rfl64((uint64_t)offsets[inst]);
+        const int k = (int)tab[D_K], kp = (int)tab[D_KP], W = (int)tab[D_W], G = (int)tab[D_G];
+        const int RS = (int)tab[D_RS];
+        const int mqs = (QS == 4) ? 4 : (int)tab[D_QS];
+        const uint32_t maxf = tab[D_MAXF];
+        const uint32_t *__restrict__ rows = tab + DEV_HDR_WORDS;
+
+        if ((int64_t)inst != staged) {
+            // T[idx] = contribution of the low 6 Gray bits at block step
+            // s = idx & 63 with bit 5 toggled by the block parity idx >> 6.
+            for (int e = tid; e < WPM_TABLE_ROWS * RS; e += blockDim.x) {
+                const int idx = e / RS, w = e - idx * RS;
+                const int s = idx & 63;
+                const uint32_t xl = (uint32_t)(s ^ (s >> 1)) ^ ((uint32_t)(idx >> 6) << 5);
+                uint32_t v = 0;
+#pragma unroll
+                for (int t = 0; t < 6; ++t)
+                    if ((xl >> t) & 1u) v ^= rows[t * RS + w];
+                lds_T[e] = v;
+            }
+            __syncthreads();
+            staged = inst;
+        }
+
+        if ((tid & ~63) < lanes) {
+            const bool active = tid < lanes;
+            const uint64_t j = first + (uint64_t)tid;
+            const uint64_t i0 = active ? (j << c) : 0;
+            const uint64_t x0 = i0 ^ (i0 >> 1);
+            uint32_t P[PW];
+#pragma unroll
+            for (int q = 0; q < PW; ++q) P[q] = 0;
+            for (int t = 6; t < kp; ++t) {
+                const uint32_t msk = 0u - (uint32_t)((x0 >> t) & 1ull);
+                xor_row<GM, QS, WM>(P, rows + t * RS, msk, G, W, mqs);
+            }
+            uint32_t s0 = P[0], s1 = P[1], s2 = P[2], s3 = P[3];
+            uint32_t d[6][4];
+#pragma unroll
+            for (int t = 0; t < 6; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) d[t][q] = __builtin_amdgcn_readfirstlane(rows[t * RS + q]);
+
+            const uint64_t nblk = 1ull << (c - 6);
+            const int koff = 4 + (G - 1) * mqs;
+            for (uint64_t blk = 0; blk < nblk; ++blk) {
+                // ---- phase 1: fast filter over 64 Gray steps
+                uint64_t fire = 0;
+#pragma unroll
+                for (int s = 0; s < 64; ++s) {
+                    const uint32_t f = fail4(s0, s1, s2, s3);
+                    // inactive lanes may set a bit too; phase 2 masks them out
+                    if (__builtin_amdgcn_ballot_w64(f == 0u)) fire |= 1ull << s;
+                    if (s < 63) {
+                        const int t = __builtin_ctz((unsigned)(s + 1));
+                        s0 ^= d[t][0];
+                        s1 ^= d[t][1];
+                        s2 ^= d[t][2];
+                        s3 ^= d[t][3];
+                    }
+                }
+                // ---- phase 2: exact check of the recorded steps
+                while (fire) {
+                    const int s = __builtin_ctzll(fire);
+                    fire &= fire - 1;
+                    ++n_fire;
+                    const int idx = ((int)(blk & 1ull) << 6) | s;
+                    const uint32_t *T = lds_T + idx * RS;
+                    bool pass = active && fail4(P[0] ^ T[0], P[1] ^ T[1], P[2] ^ T[2], P[3] ^ T[3]) == 0u;
+                    // groups in decreasing rejection order; stop once no lane passes
+                    bool go = true;
+#pragma unroll
+                    for (int g = 1; g < GM; ++g) {
+                        go = go && g < G && __builtin_amdgcn_ballot_w64(pass) != 0;
+                        if (go) {
+                            uint32_t st[QS];
+#pragma unroll
+                            for (int q = 0; q < QS; ++q)
+                                st[q] = (QS == 4 || q < mqs)
+                                            ? P[4 + (g - 1) * QS + q] ^ T[4 + (g - 1) * mqs + q]
+                                            : 0u;
+                            pass = pass && fail_slots<QS>(st) == 0u;
+                        }
+                    }
+                    const uint64_t i = i0 + (blk << 6) + (uint64_t)s;
+                    const uint64_t x = i ^ (i >> 1);
+                    pass = pass && x != 0 && (k >= 64 || (x >> k) == 0);
+                    if (__builtin_amdgcn_ballot_w64(pass)) {
+                        uint32_t cnt = 0;
+#pragma unroll
+                        for (int w = 0; w < WM; ++w)
+                            if (w < W) cnt += __builtin_popcount(P[KR + w] ^ T[koff + w]);
+                        const bool ok = pass && (maxf == 0u || cnt <= maxf);
+                        const uint64_t pball = __builtin_amdgcn_ballot_w64(pass);
+                        const uint64_t bal = __builtin_amdgcn_ballot_w64(ok);
+                        n_ridge += (uint32_t)__builtin_popcountll(pball);
+                        n_ubt += (uint32_t)__builtin_popcountll(pball & ~bal);
+                        if (bal) {
+                            const uint32_t nb = (uint32_t)__builtin_popcountll(bal);
+                            unsigned long long base = 0;
+                            if (lane == 0) {
+                                base = atomicAdd(a.total, (unsigned long long)nb);
+                                atomicAdd(a.counts + inst, (unsigned long long)nb);
+                            }
+                            base = rfl64(base);
+                            if (ok) {
+                                const uint32_t rk = __builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                                const uint64_t pos = base + rk;
+                                if (pos < a.cap) {
+                                    a.surv[2 * pos] = x;
+                                    a.surv[2 * pos + 1] = inst;
+                                }
+                            }
+                        }
+                    }
+                }
+                // ---- block boundary: one more Gray step, flipping t >= 6
+                if (blk + 1 < nblk) {
+                    const int t = 6 + __builtin_ctzll(blk + 1);
+                    const uint32_t *row = rows + t * RS;
+                    xor_row<GM, QS, WM>(P, row, ~0u, G, W, mqs);
+                    s0 ^= row[0];
+                    s1 ^= row[1];
+                    s2 ^= row[2];
+                    s3 ^= row[3];
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0 && a.times) {
+            a.times[2 * it] = t_start;
+            a.times[2 * it + 1] = __builtin_amdgcn_s_memrealtime();
+        }
+    }
+    if (a.stats && lane == 0 && (n_fire | n_ridge | n_ubt)) {
+        atomicAdd(a.stats + 0, (unsigned long long)n_fire);
+        atomicAdd(a.stats + 1, (unsigned long long)n_ridge);
+        atomicAdd(a.stats + 2, (unsigned long long)n_ubt);
+    }
+}
+
+}  // namespace wpm

@@ -1,0 +1,321 @@
+"""Python driver over the C ABI: instance preparation, device batches, sweep.
+
+PyTorch provides device memory and the stream only; every step of the
+enumeration runs in libwpm.so (host preparation in C++, the sweep in HIP).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib as L
+
+_POOL_THREADS = int(os.environ.get("WPM_PREP_THREADS", str(min(16, os.cpu_count() or 4))))
+
+
+def _ptr(a: np.ndarray, t=L.c_u32p):
+    return a.ctypes.data_as(t)
+
+
+def ubt_bound(n: int) -> int:
+    return int(L.lib().wpm_ubt_bound(n))
+
+
+def default_max_facets(n: int, m: int) -> int:
+    """Algorithm 4.4 applies the upper-bound property at Picard number 4."""
+    return ubt_bound(n) if m == n + 4 else 0
+
+
+def candidates(n: int, m: int, lam: Sequence[int]) -> np.ndarray:
+    lib = L.lib()
+    la = np.ascontiguousarray(np.asarray(lam, dtype=np.uint32))
+    Mo = ctypes.c_int32(0)
+    cap = 2048
+    while True:
+        out = np.zeros(cap, dtype=np.uint32)
+        st = lib.wpm_build_candidates(n, m, _ptr(la), _ptr(out), cap, ctypes.byref(Mo))
+        if st == L.WPM_ECAP:
+            cap = Mo.value
+            continue
+        L.check("wpm_build_candidates", st)
+        return out[:Mo.value].copy()
+
+
+def kernel_basis(n: int, m: int, facets: np.ndarray) -> Tuple[np.ndarray, np.ndarray, int]:
+    """(ridges, basis[k, W], k)."""
+    lib = L.lib()
+    F = np.ascontiguousarray(facets, dtype=np.uint32)
+    M = len(F)
+    W = (M + 31) // 32
+    No = ctypes.c_int32(0)
+    ko = ctypes.c_int32(0)
+    cap_r = max(1, M * n)
+    ridges = np.zeros(cap_r, dtype=np.uint32)
+    st = lib.wpm_kernel_basis(n, m, _ptr(F), M, _ptr(ridges), cap_r, ctypes.byref(No), None, 0,
+                              ctypes.byref(ko))
+    L.check("wpm_kernel_basis", st, (L.WPM_OK, L.WPM_ECAP))
+    k = ko.value
+    basis = np.zeros(max(1, k * W), dtype=np.uint32)
+    st = lib.wpm_kernel_basis(n, m, _ptr(F), M, _ptr(ridges), cap_r, ctypes.byref(No),
+                              _ptr(basis), k, ctypes.byref(ko))
+    L.check("wpm_kernel_basis", st)
+    return ridges[:No.value].copy(), basis[:k * W].reshape(k, W) if W else basis[:0].reshape(0, 0), k
+
+
+@dataclass
+class Prepared:
+    n: int
+    m: int
+    facets: np.ndarray
+    k: int
+    basis: np.ndarray           # [k, W] uint32
+    N: int
+    max_facets: int
+    table: Optional[np.ndarray] = None
+    info: Optional[L.InstanceInfo] = None
+    tag: str = ""
+
+    @property
+    def W(self) -> int:
+        return (len(self.facets) + 31) // 32
+
+    @property
+    def vectors(self) -> int:
+        return 1 << self.k
+
+
+def prepare(n: int, m: int, lam: Optional[Sequence[int]] = None,
+            facets: Optional[Sequence[int]] = None, max_facets: Optional[int] = None,
+            seed: int = 0, pack: bool = True) -> Prepared:
+    """Candidates (if lambda is given), ridges, kernel basis and packed table."""
+    if facets is None:
+        F = candidates(n, m, lam)
+    else:
+        F = np.ascontiguousarray(np.asarray(facets, dtype=np.uint32))
+    if max_facets is None:
+        max_facets = default_max_facets(n, m)
+    ridges, B, k = kernel_basis(n, m, F)
+    p = Prepared(n=n, m=m, facets=F, k=k, basis=np.ascontiguousarray(B), N=len(ridges),
+                 max_facets=max_facets)
+    if pack:
+        pack_prepared(p, seed)
+    return p
+
+
+def pack_prepared(p: Prepared, seed: int = 0) -> None:
+    lib = L.lib()
+    info = L.InstanceInfo()
+    Bf = np.ascontiguousarray(p.basis.reshape(-1), dtype=np.uint32)
+    if Bf.size == 0:
+        Bf = np.zeros(1, dtype=np.uint32)
+    st = lib.wpm_pack_instance(p.n, p.m, _ptr(p.facets), len(p.facets), _ptr(Bf), p.k,
+                               p.max_facets, seed, None, 0, ctypes.byref(info))
+    L.check("wpm_pack_instance", st, (L.WPM_ECAP,))
+    tab = np.zeros(info.table_words, dtype=np.uint32)
+    st = lib.wpm_pack_instance(p.n, p.m, _ptr(p.facets), len(p.facets), _ptr(Bf), p.k,
+                               p.max_facets, seed, _ptr(tab), info.table_words, ctypes.byref(info))
+    L.check("wpm_pack_instance", st)
+    p.table, p.info = tab, info
+
+
+def kdim(inst) -> int:
+    """Kernel dimension of a wpm_inputs.Instance with this engine's own code."""
+    F = candidates(inst.n, inst.m, inst.lam) if inst.facets is None else np.asarray(inst.facets, np.uint32)
+    return kernel_basis(inst.n, inst.m, F)[2]
+
+
+def prepare_many(insts, seed: int = 0, threads: int = _POOL_THREADS) -> List[Prepared]:
+    """prepare() over wpm_inputs.Instance objects, in parallel host threads
+    (the C calls release the GIL)."""
+    def one(a):
+        i, inst = a
+        p = prepare(inst.n, inst.m, lam=inst.lam, facets=inst.facets, seed=seed + i)
+        p.tag = inst.tag
+        return p
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        return list(ex.map(one, enumerate(insts)))
+
+
+def device_query():
+    cus = ctypes.c_int32(0)
+    clk = ctypes.c_int64(0)
+    lds = ctypes.c_int32(0)
+    L.check("wpm_device_query", L.lib().wpm_device_query(ctypes.byref(cus), ctypes.byref(clk),
+                                                         ctypes.byref(lds)))
+    return cus.value, clk.value, lds.value
+
+
+class DeviceBatch:
+    """Packed tables of a list of prepared instances, resident in HBM."""
+
+    def __init__(self, preps: Sequence[Prepared], device="cuda"):
+        import torch
+        self.preps = list(preps)
+        sizes = [int(p.info.table_words) for p in self.preps]
+        padded = [(s + 3) & ~3 for s in sizes]
+        offs = np.zeros(len(self.preps), dtype=np.int64)
+        if len(self.preps) > 1:
+            offs[1:] = np.cumsum(padded[:-1])
+        total = int(sum(padded)) if self.preps else 4
+        host = np.zeros(max(total, 4), dtype=np.uint32)
+        for p, o in zip(self.preps, offs):
+            host[o:o + len(p.table)] = p.table
+        self.tables = torch.from_numpy(host.view(np.int32)).to(device)
+        self.offsets = torch.from_numpy(offs).to(device)
+        self.k = np.array([p.k for p in self.preps], dtype=np.int32)
+        self.c_batch = L.Batch(
+            num_instances=len(self.preps),
+            max_row_words=max([p.info.row_words for p in self.preps] + [4]),
+            max_groups=max([p.info.groups for p in self.preps] + [1]),
+            max_slots=max([p.info.slots for p in self.preps] + [4]),
+            max_words=max([p.info.W for p in self.preps] + [1]),
+            reserved=0,
+            d_tables=self.tables.data_ptr(), d_offsets=self.offsets.data_ptr())
+        self.table_bytes = total * 4
+
+    @property
+    def vectors(self) -> int:
+        return int(sum(1 << int(k) for k in self.k))
+
+
+def build_queue(k: np.ndarray, cbits: int, lanes: int, cost: Optional[np.ndarray] = None,
+                max_items_per_instance: int = 0, order: int = 0) -> np.ndarray:
+    lib = L.lib()
+    ka = np.ascontiguousarray(k, dtype=np.int32)
+    ca = None if cost is None else np.ascontiguousarray(cost, dtype=np.float32)
+    n = ctypes.c_int64(0)
+    cp = None if ca is None else _ptr(ca, L.c_f32p)
+    st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, len(ka), cbits, lanes, max_items_per_instance,
+                             order, None, 0, ctypes.byref(n))
+    L.check("wpm_build_queue", st, (L.WPM_ECAP, L.WPM_OK))
+    items = (L.Item * max(1, n.value))()
+    st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, len(ka), cbits, lanes, max_items_per_instance,
+                             order, items, n.value, ctypes.byref(n))
+    L.check("wpm_build_queue", st)
+    arr = np.frombuffer(items, dtype=np.dtype([("instance", "<u4"), ("cbits", "<u2"),
+                                               ("lanes", "<u2"), ("first", "<u8")]),
+                        count=n.value).copy()
+    return arr
+
+
+@dataclass
+class SweepResult:
+    counts: np.ndarray
+    total: int
+    stats: np.ndarray
+    ms: float = 0.0
+    item_times: Optional[np.ndarray] = None
+    items: Optional[np.ndarray] = None
+
+
+class Sweeper:
+    """Device buffers and one call of wpm_enumerate over a DeviceBatch."""
+
+    def __init__(self, batch: DeviceBatch, cap: int = 1 << 20, device="cuda"):
+        import torch
+        self.torch = torch
+        self.batch = batch
+        self.cap = cap
+        self.surv = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=device)
+        self.counts = torch.empty(max(1, len(batch.preps)), dtype=torch.int64, device=device)
+        self.total = torch.empty(1, dtype=torch.int64, device=device)
+        self.stats = torch.empty(8, dtype=torch.int64, device=device)
+        self.scratch = torch.empty(4, dtype=torch.int64, device=device)
+        self._items_dev = None
+        self._items_host = None
+        self._times = None
+
+    def set_items(self, items: np.ndarray, want_times: bool = False):
+        torch = self.torch
+        self._items_host = np.ascontiguousarray(items)
+        raw = self._items_host.view(np.int64).reshape(-1) if len(items) else np.zeros(2, np.int64)
+        self._items_dev = torch.from_numpy(raw.copy()).to(self.surv.device)
+        self._times = (torch.zeros((max(1, len(items)), 2), dtype=torch.int64, device=self.surv.device)
+                       if want_times else None)
+
+    def launch(self, mode: int, wg_size: int = 256, grid: int = 0, stream=None) -> None:
+        torch = self.torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        items = self._items_host
+        s = L.Sched(mode=mode, wg_size=wg_size, grid=grid, reserved=0,
+                    d_items=self._items_dev.data_ptr(),
+                    h_items=items.ctypes.data if len(items) else None,
+                    num_items=len(items), d_scratch=self.scratch.data_ptr(),
+                    d_item_times=self._times.data_ptr() if self._times is not None else None)
+        st = L.lib().wpm_enumerate(ctypes.byref(self.batch.c_batch), ctypes.byref(s),
+                                   self.surv.data_ptr(), self.cap, self.counts.data_ptr(),
+                                   self.total.data_ptr(), self.stats.data_ptr(),
+                                   ctypes.c_void_p(stream.cuda_stream))
+        L.check("wpm_enumerate", st)
+
+    def result(self) -> SweepResult:
+        self.torch.cuda.synchronize()
+        counts = self.counts[:len(self.batch.preps)].cpu().numpy().astype(np.uint64)
+        return SweepResult(counts=counts, total=int(self.total.item()),
+                           stats=self.stats.cpu().numpy(),
+                           item_times=None if self._times is None else self._times.cpu().numpy(),
+                           items=self._items_host)
+
+    def collect(self, stream=None) -> List[List[Tuple[int, ...]]]:
+        """Per instance, the canonical list of results (sorted tuples of facet masks)."""
+        torch = self.torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        preps = self.batch.preps
+        hosts = (L.HostInstance * max(1, len(preps)))()
+        keep = []
+        for i, p in enumerate(preps):
+            Bf = np.ascontiguousarray(p.basis.reshape(-1), dtype=np.uint32)
+            if Bf.size == 0:
+                Bf = np.zeros(1, np.uint32)
+            keep.append(Bf)
+            hosts[i] = L.HostInstance(M=len(p.facets), k=p.k, facets=p.facets.ctypes.data,
+                                      basis=Bf.ctypes.data)
+        h_counts = np.zeros(max(1, len(preps)), dtype=np.uint64)
+        offs = np.zeros(len(preps) + 1, dtype=np.int64)
+        words = ctypes.c_int64(0)
+        lib = L.lib()
+        args = (hosts, len(preps), self.surv.data_ptr(), self.cap, self.counts.data_ptr(),
+                self.total.data_ptr(), _ptr(h_counts, L.c_u64p))
+        st = lib.wpm_collect(*args, None, 0, ctypes.byref(words), _ptr(offs, L.c_i64p),
+                             ctypes.c_void_p(stream.cuda_stream))
+        L.check("wpm_collect", st, (L.WPM_ECAP, L.WPM_OK))
+        if words.value < 0:
+            raise L.WpmError("wpm_collect (survivor buffer overflow)", L.WPM_ECAP)
+        out = np.zeros(max(1, words.value), dtype=np.uint32)
+        st = lib.wpm_collect(*args, _ptr(out), words.value, ctypes.byref(words),
+                             _ptr(offs, L.c_i64p), ctypes.c_void_p(stream.cuda_stream))
+        L.check("wpm_collect", st)
+        res = []
+        for i in range(len(preps)):
+            a, b = int(offs[i]), int(offs[i + 1])
+            lst = []
+            w = a
+            while w < b:
+                ln = int(out[w])
+                lst.append(tuple(int(v) for v in out[w + 1:w + 1 + ln]))
+                w += 1 + ln
+            res.append(lst)
+        return res
+
+
+def sweep(preps: Sequence[Prepared], mode: int = L.SCHED_DYNAMIC, cbits: int = 12,
+          wg_size: int = 256, grid: int = 0, cap: int = 1 << 20, order: int = 0,
+          cost: Optional[np.ndarray] = None, max_items_per_instance: int = 0,
+          want_sets: bool = True):
+    """Convenience: upload, sweep, collect.  Returns (SweepResult, sets or None)."""
+    batch = DeviceBatch(preps)
+    sw = Sweeper(batch, cap=cap)
+    items = build_queue(batch.k, cbits, wg_size, cost=cost,
+                        max_items_per_instance=max_items_per_instance, order=order)
+    sw.set_items(items)
+    sw.launch(mode, wg_size=wg_size, grid=grid)
+    res = sw.result()
+    sets = sw.collect() if want_sets else None
+    return res, sets

@@ -1,0 +1,114 @@
+"""CPU interpreter of the packed instance table (host-logic tests only).
+
+It evaluates, for every kernel vector x of a small instance, the same
+predicate the GPU sweep evaluates from the table: the bit-sliced ridge slots
+(at least 3 of a ridge's slot bits set = the ridge has degree 4), the facet
+count bound and x != 0.  It also replays the kernel's two-phase walk over Gray
+blocks (incremental fast-filter state, per-block base P, low-part table T) so
+the walk's bookkeeping is checked without a GPU.
+"""
+import numpy as np
+
+HDR = 16
+
+
+def header(tab):
+    h = [int(v) for v in tab[:HDR]]
+    return dict(k=h[1], kp=h[2], M=h[3], W=h[4], G=h[5], QS=h[6], RS=h[7], maxf=h[8])
+
+
+def rows(tab):
+    h = header(tab)
+    return tab[HDR:HDR + h["kp"] * h["RS"]].reshape(h["kp"], h["RS"]).astype(np.uint64)
+
+
+def at_least3(words):
+    c1 = np.zeros_like(words[0]); c2 = np.zeros_like(words[0]); c3 = np.zeros_like(words[0])
+    for w in words:
+        c3 |= c2 & w
+        c2 |= c1 & w
+        c1 |= w
+    return c3
+
+
+def state(R, x):
+    v = np.zeros(R.shape[1], dtype=np.uint64)
+    t = 0
+    while x:
+        if x & 1:
+            v ^= R[t]
+        x >>= 1
+        t += 1
+    return v
+
+
+def accept(h, v):
+    if at_least3([v[0], v[1], v[2], v[3]]) != 0:
+        return False
+    for g in range(1, h["G"]):
+        base = 4 + (g - 1) * h["QS"]
+        if at_least3([v[base + q] for q in range(h["QS"])]) != 0:
+            return False
+    koff = 4 + (h["G"] - 1) * h["QS"]
+    cnt = sum(bin(int(v[koff + w])).count("1") for w in range(h["W"]))
+    return h["maxf"] == 0 or cnt <= h["maxf"]
+
+
+def survivors_direct(tab):
+    h = header(tab)
+    R = rows(tab)
+    return sorted(x for x in range(1, 1 << h["k"]) if accept(h, state(R, x)))
+
+
+def survivors_walk(tab, cbits=7):
+    """Replays the GPU walk: lanes = chunks of 2^cbits Gray indices."""
+    h = header(tab)
+    R = rows(tab)
+    kp, k = h["kp"], h["k"]
+    c = min(max(cbits, 7), kp)
+    T = np.zeros((128, R.shape[1]), dtype=np.uint64)
+    for idx in range(128):
+        s = idx & 63
+        xl = (s ^ (s >> 1)) ^ ((idx >> 6) << 5)
+        T[idx] = state(R[:6], xl)
+    out = []
+    for j in range(1 << (kp - c)):
+        i0 = j << c
+        x0 = i0 ^ (i0 >> 1)
+        P = state(R, x0 & ~63)
+        assert (x0 & 63) == 0
+        s4 = P[:4].copy()
+        for blk in range(1 << (c - 6)):
+            fire = []
+            for s in range(64):
+                if at_least3(list(s4)) == 0:
+                    fire.append(s)
+                if s < 63:
+                    t = (s + 1 & -(s + 1)).bit_length() - 1
+                    s4 ^= R[t, :4]
+            for s in fire:
+                idx = ((blk & 1) << 6) | s
+                v = P ^ T[idx]
+                i = i0 + (blk << 6) + s
+                x = i ^ (i >> 1)
+                assert np.array_equal(v, state(R, x))
+                if x and (x >> k) == 0 and accept(h, v):
+                    out.append(x)
+            if blk + 1 < (1 << (c - 6)):
+                t = 6 + ((blk + 1) & -(blk + 1)).bit_length() - 1
+                P ^= R[t]
+                s4 ^= R[t, :4]
+    return sorted(out)
+
+
+def facets_of_x(basis, facets, x):
+    W = basis.shape[1] if basis.ndim == 2 else 0
+    K = np.zeros(W, dtype=np.uint32)
+    t = 0
+    while x:
+        if x & 1:
+            K ^= basis[t]
+        x >>= 1
+        t += 1
+    return tuple(sorted(int(facets[w * 32 + b]) for w in range(W) for b in range(32)
+                        if (int(K[w]) >> b) & 1))

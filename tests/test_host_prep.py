@@ -1,0 +1,129 @@
+"""Host-side engine logic against the oracle (no GPU needed).
+
+The packed table is interpreted on the CPU (tests/tablesim.py) and its
+accepted set compared with the oracle's enumeration; candidates, ridges and
+kernel dimensions are compared with the oracle's own routines.
+"""
+import ctypes
+import itertools
+import random
+
+import numpy as np
+import pytest
+
+import oracle as O
+import wpm_inputs as W
+from paper_2301_00806_amd import _lib as L
+from paper_2301_00806_amd import engine as E
+import tablesim as TS
+
+
+def test_library_exports_every_declared_symbol():
+    import re, os
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "wpm.h")).read()
+    declared = set(re.findall(r"\b(wpm_[a-z_]+)\s*\(", hdr))
+    lib = L.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(L.EXPORTED)
+
+
+def test_strerror_codes():
+    lib = L.lib()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.wpm_strerror(code)
+    assert lib.wpm_strerror(-99) == b"unknown status"
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_candidates_ridges_k_match_oracle(seed):
+    rng = random.Random(seed)
+    n = rng.randint(2, 7)
+    m = n + rng.randint(1, 5)
+    lam = [rng.randrange(1 << n) for _ in range(m)]
+    F = E.candidates(n, m, lam)
+    assert list(F) == O.candidates(n, m, lam)
+    if len(F) == 0 or n < 2:
+        return
+    ridges, B, k = E.kernel_basis(n, m, F)
+    assert list(ridges) == O.ridges(n, list(F))
+    assert k == O.kernel_dim(n, list(F))
+    # every basis vector is in the kernel: each ridge meets it evenly
+    for t in range(k):
+        chosen = [int(F[j]) for j in range(len(F)) if (int(B[t, j // 32]) >> (j % 32)) & 1]
+        for r in ridges:
+            assert sum(1 for f in chosen if f & int(r) == int(r)) % 2 == 0
+
+
+def test_ubt_bound_matches_oracle():
+    for n in range(2, 12):
+        assert E.ubt_bound(n) == O.ubt_bound(n)
+
+
+def _instances_small():
+    out = [("fano", 3, 7, W.fano().lam, None)]
+    out.append(("octa", 2, 6, [1, 2, 1, 2, 3, 3], None))
+    k5 = [(1 << a) | (1 << b) for a, b in itertools.combinations(range(6), 2)]
+    out.append(("K6", 2, 6, None, k5))
+    for i, inst in enumerate(W.batch(O.kdim_of, count=8)):
+        if inst.meta["k"] <= 14:
+            out.append((f"batch{i}", inst.n, inst.m, inst.lam, None))
+    return out
+
+
+@pytest.mark.parametrize("case", _instances_small(), ids=lambda c: c[0])
+def test_packed_table_semantics_match_oracle(case):
+    name, n, m, lam, facets = case
+    p = E.prepare(n, m, lam=lam, facets=facets)
+    mf = p.max_facets
+    want = O.enumerate_wpm(n, [int(f) for f in p.facets], mf)
+    got_x = TS.survivors_direct(p.table)
+    got = sorted(TS.facets_of_x(p.basis, p.facets, x) for x in got_x)
+    assert got == want
+    assert TS.survivors_walk(p.table, cbits=7) == got_x
+
+
+def test_walk_with_larger_chunks():
+    inst = [i for i in W.batch(O.kdim_of, count=16) if 12 <= i.meta["k"] <= 13][0]
+    p = E.prepare(inst.n, inst.m, lam=inst.lam)
+    assert TS.survivors_walk(p.table, cbits=9) == TS.survivors_direct(p.table)
+
+
+def test_pack_rejects_large_k_and_bad_input():
+    lib = L.lib()
+    info = L.InstanceInfo()
+    F = np.array([0b011, 0b101, 0b110], dtype=np.uint32)
+    B = np.zeros(70 * 1, dtype=np.uint32)
+    st = lib.wpm_pack_instance(2, 3, E._ptr(F), 3, E._ptr(B), 70, 0, 0, None, 0, ctypes.byref(info))
+    assert st == L.WPM_EKMAX
+    bad = np.array([0b011, 0b011], dtype=np.uint32)  # duplicate facet
+    st = lib.wpm_pack_instance(2, 3, E._ptr(bad), 2, E._ptr(B), 0, 0, 0, None, 0, ctypes.byref(info))
+    assert st == L.WPM_EINVAL
+    wrong = np.array([0b111], dtype=np.uint32)  # size 3, n = 2
+    No, ko = ctypes.c_int32(), ctypes.c_int32()
+    st = lib.wpm_kernel_basis(2, 3, E._ptr(wrong), 1, None, 0, ctypes.byref(No), None, 0, ctypes.byref(ko))
+    assert st == L.WPM_EINVAL
+    lam = np.array([1, 2, 9], dtype=np.uint32)  # column 9 has bits above n = 2
+    Mo = ctypes.c_int32()
+    out = np.zeros(8, np.uint32)
+    assert lib.wpm_build_candidates(2, 3, E._ptr(lam), E._ptr(out), 8, ctypes.byref(Mo)) == L.WPM_EINVAL
+
+
+def test_build_queue_covers_every_chunk_once():
+    k = np.array([7, 12, 20, 9], dtype=np.int32)
+    for cb, lanes, mx, order in [(7, 64, 0, 0), (10, 256, 0, 1), (7, 128, 4, 1)]:
+        items = E.build_queue(k, cb, lanes, cost=np.array([1, 2, 3, 4], np.float32),
+                              max_items_per_instance=mx, order=order)
+        for i, kk in enumerate(k):
+            mine = items[items["instance"] == i]
+            covered = sum(int(it["lanes"]) << int(it["cbits"]) for it in mine)
+            assert covered == 1 << max(int(kk), 7)
+            spans = sorted((int(it["first"]) << int(it["cbits"]),
+                            (int(it["first"]) + int(it["lanes"])) << int(it["cbits"])) for it in mine)
+            for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
+                assert a1 == b0
+            if mx:
+                assert len(mine) <= mx
+        if order == 1:
+            cost = [float([1, 2, 3, 4][it["instance"]]) * (int(it["lanes"]) << int(it["cbits"])) for it in items]
+            assert cost == sorted(cost, reverse=True)
