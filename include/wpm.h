@@ -166,14 +166,17 @@ enum {
  *                    cost is cost[i] * vectors in the item
  *   cbits            lane chunk bits (clamped to [7, max(k,7)] per instance)
  *   lanes            lanes per item (workgroup size)
+ *   min_items_per_instance  lower cbits (down to 7) until an instance has at
+ *                    least this many full items (values < 1 count as 1), so a
+ *                    small instance still occupies whole workgroups
  *   max_items_per_instance  > 0: coarsen chunks so an instance yields at most
- *                    this many items (raises cbits)
+ *                    this many items (raises cbits; applied after the minimum)
  *   order            0 = instance order, 1 = descending item cost (LPT)
  *   items, cap       output (host); *n_out = item count (WPM_ECAP if > cap)
  */
 int wpm_build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits,
-                    int32_t lanes, int32_t max_items_per_instance, int32_t order,
-                    wpm_item *items, int64_t cap, int64_t *n_out);
+                    int32_t lanes, int32_t min_items_per_instance, int32_t max_items_per_instance,
+                    int32_t order, wpm_item *items, int64_t cap, int64_t *n_out);
 
 /* Device-resident batch. */
 typedef struct wpm_batch {
@@ -182,7 +185,7 @@ typedef struct wpm_batch {
     int32_t max_groups;        /* max info.groups */
     int32_t max_slots;         /* max info.slots (4 or 8) */
     int32_t max_words;         /* max info.W */
-    int32_t reserved;
+    int32_t max_kp;            /* max over the batch of max(k, 7) (LDS sizing) */
     const uint32_t *d_tables;  /* device: packed tables, concatenated (16-byte aligned each) */
     const int64_t *d_offsets;  /* device: word offset of each table in d_tables */
 } wpm_batch;

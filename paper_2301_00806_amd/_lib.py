@@ -37,7 +37,7 @@ class Item(ctypes.Structure):
 class Batch(ctypes.Structure):
     _fields_ = [("num_instances", ctypes.c_int32), ("max_row_words", ctypes.c_int32),
                 ("max_groups", ctypes.c_int32), ("max_slots", ctypes.c_int32),
-                ("max_words", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_words", ctypes.c_int32), ("max_kp", ctypes.c_int32),
                 ("d_tables", ctypes.c_void_p), ("d_offsets", ctypes.c_void_p)]
 
 
@@ -92,7 +92,7 @@ def lib():
                                     ctypes.c_int64, ctypes.POINTER(InstanceInfo)]
     L.wpm_build_queue.restype = ctypes.c_int
     L.wpm_build_queue.argtypes = [c_i32p, c_f32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                  ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Item),
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Item),
                                   ctypes.c_int64, c_i64p]
     L.wpm_enumerate.restype = ctypes.c_int
     L.wpm_enumerate.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Sched), ctypes.c_void_p,

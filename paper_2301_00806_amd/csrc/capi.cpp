@@ -47,10 +47,10 @@ int wpm_pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uin
 }
 
 int wpm_build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits,
-                    int32_t lanes, int32_t max_items_per_instance, int32_t order,
-                    wpm_item *items, int64_t cap, int64_t *n_out) {
-    return wpm::build_queue(k, cost, num, cbits, lanes, max_items_per_instance, order, items, cap,
-                            n_out);
+                    int32_t lanes, int32_t min_items_per_instance, int32_t max_items_per_instance,
+                    int32_t order, wpm_item *items, int64_t cap, int64_t *n_out) {
+    return wpm::build_queue(k, cost, num, cbits, lanes, min_items_per_instance,
+                            max_items_per_instance, order, items, cap, n_out);
 }
 
 int wpm_enumerate(const wpm_batch *batch, const wpm_sched *sched, uint64_t *d_survivors,

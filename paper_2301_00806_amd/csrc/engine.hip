@@ -95,6 +95,7 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     if (b->max_groups < 1 || b->max_groups > WPM_MAX_GROUPS) return WPM_EINVAL;
     if (b->max_slots != 4 && b->max_slots != 8) return WPM_EINVAL;
     if (b->max_words < 0 || b->max_words > 32 || b->max_row_words < 4) return WPM_EINVAL;
+    if (b->max_kp < 7 || b->max_kp > WPM_MAX_K) return WPM_EINVAL;
     if (s->wg_size < 64 || s->wg_size > 1024 || (s->wg_size % 64)) return WPM_EINVAL;
     if (s->num_items < 0 || (s->num_items > 0 && !s->d_items)) return WPM_EINVAL;
     if (s->mode < WPM_SCHED_PLAIN || s->mode > WPM_SCHED_DYNAMIC) return WPM_EINVAL;
@@ -102,7 +103,8 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     if (s->mode == WPM_SCHED_DYNAMIC && !s->d_scratch) return WPM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const int gm = pick_gm(b->max_groups), qs = b->max_slots, wm = pick_wm(b->max_words);
-    const size_t lds = (size_t)WPM_TABLE_ROWS * (size_t)b->max_row_words * sizeof(uint32_t);
+    const size_t lds =
+        (size_t)(WPM_TABLE_ROWS + b->max_kp) * (size_t)b->max_row_words * sizeof(uint32_t);
     int32_t lds_max = 0;
     int rc = device_query(nullptr, nullptr, &lds_max);
     if (rc) return rc;

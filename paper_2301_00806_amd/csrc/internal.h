@@ -50,8 +50,8 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
 void cost_features(const wpm_instance_info &info, const Incidence &inc,
                    const std::vector<int32_t> &crit, float *out);
 int build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits, int32_t lanes,
-                int32_t max_items_per_instance, int32_t order, wpm_item *items, int64_t cap,
-                int64_t *n_out);
+                int32_t min_items_per_instance, int32_t max_items_per_instance, int32_t order,
+                wpm_item *items, int64_t cap, int64_t *n_out);
 
 void set_hip_error(const char *what, int code, const char *text);
 

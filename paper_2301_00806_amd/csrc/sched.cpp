@@ -16,8 +16,8 @@
 namespace wpm {
 
 int build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits, int32_t lanes,
-                int32_t max_items_per_instance, int32_t order, wpm_item *items, int64_t cap,
-                int64_t *n_out) {
+                int32_t min_items_per_instance, int32_t max_items_per_instance, int32_t order,
+                wpm_item *items, int64_t cap, int64_t *n_out) {
     if (!k || !n_out || num < 0 || lanes < 1 || lanes > 1024 || cbits < 0 || order < 0 ||
         order > 1)
         return WPM_EINVAL;
@@ -37,6 +37,10 @@ int build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits,
             const uint64_t chunks = 1ull << cb;
             return (chunks + lanes - 1) / lanes;
         };
+        // shrink chunks until the instance fills min_items full workgroups ...
+        const uint64_t want = (uint64_t)std::max(1, min_items_per_instance) * (uint64_t)lanes;
+        while (c > 7 && kp - c < 62 && (1ull << (kp - c)) < want) --c;
+        // ... but never split it into more than max_items items
         if (max_items_per_instance > 0)
             while (c < kp && n_items(c) > (uint64_t)max_items_per_instance) ++c;
         const uint64_t ni = n_items(c);

@@ -117,15 +117,23 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
 template <int GM, int QS, int WM>
 __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__ tables,
                                                      const int64_t *__restrict__ offsets,
-                                                     const wpm_item *__restrict__ items, KArgs a) {
-    extern __shared__ uint32_t lds_T[];  // [128][RS]
+                                                     const wpm_item *__restrict__ items, KArgs a_in) {
+    extern __shared__ uint32_t lds_T[];  // [128][RS] low-part table, then [kp][RS] rows
     __shared__ unsigned long long s_item;
+    // The launch arguments live in LDS: phase 2 reads them there, which keeps
+    // them out of the scalar registers the fast loop needs.
+    __shared__ KArgs s_a;
+    if (threadIdx.x == 0) s_a = a_in;
+    __syncthreads();
+    const KArgs &a = s_a;
     constexpr int KR = Layout<GM, QS, WM>::KR;
     constexpr int PW = Layout<GM, QS, WM>::PW;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     int64_t staged = -1;
-    uint32_t n_fire = 0, n_ridge = 0, n_ubt = 0;  // wave-uniform statistics
+    // statistics, kept by lane 0 of each wave in VGPRs (SGPRs are the scarce
+    // resource of the fast loop)
+    uint32_t n_fire = 0, n_ridge = 0, n_ubt = 0;
 
     for (int64_t round = 0;; ++round) {
         int64_t it;
@@ -155,24 +163,32 @@ __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__
         const uint32_t maxf = tab[D_MAXF];
         const uint32_t *__restrict__ rows = tab + DEV_HDR_WORDS;
 
+        uint32_t *lds_R = lds_T + WPM_TABLE_ROWS * RS;  // [kp][RS] basis rows
         if ((int64_t)inst != staged) {
             // T[idx] = contribution of the low 6 Gray bits at block step
-            // s = idx & 63 with bit 5 toggled by the block parity idx >> 6.
-            for (int e = tid; e < WPM_TABLE_ROWS * RS; e += blockDim.x) {
-                const int idx = e / RS, w = e - idx * RS;
-                const int s = idx & 63;
-                const uint32_t xl = (uint32_t)(s ^ (s >> 1)) ^ ((uint32_t)(idx >> 6) << 5);
+            // s = idx & 63 with bit 5 toggled by the block parity idx >> 6;
+            // then a copy of the basis rows themselves.
+            const int nT = WPM_TABLE_ROWS * RS;
+            for (int e = tid; e < nT + kp * RS; e += blockDim.x) {
                 uint32_t v = 0;
+                if (e < nT) {
+                    const int idx = e / RS, w = e - idx * RS;
+                    const int s = idx & 63;
+                    const uint32_t xl = (uint32_t)(s ^ (s >> 1)) ^ ((uint32_t)(idx >> 6) << 5);
 #pragma unroll
-                for (int t = 0; t < 6; ++t)
-                    if ((xl >> t) & 1u) v ^= rows[t * RS + w];
+                    for (int t = 0; t < 6; ++t)
+                        if ((xl >> t) & 1u) v ^= rows[t * RS + w];
+                } else {
+                    v = rows[e - nT];
+                }
                 lds_T[e] = v;
             }
             __syncthreads();
             staged = inst;
         }
 
-        if ((tid & ~63) < lanes) {
+        // wave-uniform test (readfirstlane tells the compiler so)
+        if ((int)__builtin_amdgcn_readfirstlane((uint32_t)(tid & ~63)) < lanes) {
             const bool active = tid < lanes;
             const uint64_t j = first + (uint64_t)tid;
             const uint64_t i0 = active ? (j << c) : 0;
@@ -182,25 +198,30 @@ __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__
             for (int q = 0; q < PW; ++q) P[q] = 0;
             for (int t = 6; t < kp; ++t) {
                 const uint32_t msk = 0u - (uint32_t)((x0 >> t) & 1ull);
-                xor_row<GM, QS, WM>(P, rows + t * RS, msk, G, W, mqs);
+                xor_row<GM, QS, WM>(P, lds_R + t * RS, msk, G, W, mqs);
             }
             uint32_t s0 = P[0], s1 = P[1], s2 = P[2], s3 = P[3];
             uint32_t d[6][4];
 #pragma unroll
             for (int t = 0; t < 6; ++t)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) d[t][q] = __builtin_amdgcn_readfirstlane(rows[t * RS + q]);
+                for (int q = 0; q < 4; ++q) d[t][q] = __builtin_amdgcn_readfirstlane(lds_R[t * RS + q]);
 
             const uint64_t nblk = 1ull << (c - 6);
             const int koff = 4 + (G - 1) * mqs;
             for (uint64_t blk = 0; blk < nblk; ++blk) {
                 // ---- phase 1: fast filter over 64 Gray steps
+                // The step mask is set on a rarely taken branch, so a step
+                // costs 8 VALU ops and one conditional branch.
                 uint64_t fire = 0;
 #pragma unroll
                 for (int s = 0; s < 64; ++s) {
                     const uint32_t f = fail4(s0, s1, s2, s3);
                     // inactive lanes may set a bit too; phase 2 masks them out
-                    if (__builtin_amdgcn_ballot_w64(f == 0u)) fire |= 1ull << s;
+                    if (__builtin_expect(__builtin_amdgcn_ballot_w64(f == 0u) != 0, 0)) {
+                        fire |= 1ull << s;
+                        asm volatile("" : "+s"(fire));
+                    }
                     if (s < 63) {
                         const int t = __builtin_ctz((unsigned)(s + 1));
                         s0 ^= d[t][0];
@@ -213,21 +234,23 @@ __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__
                 while (fire) {
                     const int s = __builtin_ctzll(fire);
                     fire &= fire - 1;
-                    ++n_fire;
+                    if (lane == 0) ++n_fire;
                     const int idx = ((int)(blk & 1ull) << 6) | s;
                     const uint32_t *T = lds_T + idx * RS;
                     bool pass = active && fail4(P[0] ^ T[0], P[1] ^ T[1], P[2] ^ T[2], P[3] ^ T[3]) == 0u;
                     // groups in decreasing rejection order; stop once no lane passes
+                    int Gp = G, Qp = mqs;
+                    asm volatile("" : "+s"(Gp), "+s"(Qp));
                     bool go = true;
 #pragma unroll
                     for (int g = 1; g < GM; ++g) {
-                        go = go && g < G && __builtin_amdgcn_ballot_w64(pass) != 0;
+                        go = go && g < Gp && __builtin_amdgcn_ballot_w64(pass) != 0;
                         if (go) {
                             uint32_t st[QS];
 #pragma unroll
                             for (int q = 0; q < QS; ++q)
-                                st[q] = (QS == 4 || q < mqs)
-                                            ? P[4 + (g - 1) * QS + q] ^ T[4 + (g - 1) * mqs + q]
+                                st[q] = (QS == 4 || q < Qp)
+                                            ? P[4 + (g - 1) * QS + q] ^ T[4 + (g - 1) * Qp + q]
                                             : 0u;
                             pass = pass && fail_slots<QS>(st) == 0u;
                         }
@@ -236,15 +259,19 @@ __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__
                     const uint64_t x = i ^ (i >> 1);
                     pass = pass && x != 0 && (k >= 64 || (x >> k) == 0);
                     if (__builtin_amdgcn_ballot_w64(pass)) {
+                        int Wp = W, ko = koff;
+                        asm volatile("" : "+s"(Wp), "+s"(ko));
                         uint32_t cnt = 0;
 #pragma unroll
                         for (int w = 0; w < WM; ++w)
-                            if (w < W) cnt += __builtin_popcount(P[KR + w] ^ T[koff + w]);
+                            if (w < Wp) cnt += __builtin_popcount(P[KR + w] ^ T[ko + w]);
                         const bool ok = pass && (maxf == 0u || cnt <= maxf);
                         const uint64_t pball = __builtin_amdgcn_ballot_w64(pass);
                         const uint64_t bal = __builtin_amdgcn_ballot_w64(ok);
-                        n_ridge += (uint32_t)__builtin_popcountll(pball);
-                        n_ubt += (uint32_t)__builtin_popcountll(pball & ~bal);
+                        if (lane == 0) {
+                            n_ridge += (uint32_t)__builtin_popcountll(pball);
+                            n_ubt += (uint32_t)__builtin_popcountll(pball & ~bal);
+                        }
                         if (bal) {
                             const uint32_t nb = (uint32_t)__builtin_popcountll(bal);
                             unsigned long long base = 0;
@@ -267,9 +294,13 @@ __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__
                 }
                 // ---- block boundary: one more Gray step, flipping t >= 6
                 if (blk + 1 < nblk) {
+                    // opaque copy: keeps the per-group tests from being hoisted
+                    // out of the block loop as live lane masks
+                    int Gb = G, Wb = W, Qb = mqs;
+                    asm volatile("" : "+s"(Gb), "+s"(Wb), "+s"(Qb));
                     const int t = 6 + __builtin_ctzll(blk + 1);
-                    const uint32_t *row = rows + t * RS;
-                    xor_row<GM, QS, WM>(P, row, ~0u, G, W, mqs);
+                    const uint32_t *row = lds_R + t * RS;
+                    xor_row<GM, QS, WM>(P, row, ~0u, Gb, Wb, Qb);
                     s0 ^= row[0];
                     s1 ^= row[1];
                     s2 ^= row[2];

@@ -174,7 +174,7 @@ class DeviceBatch:
             max_groups=max([p.info.groups for p in self.preps] + [1]),
             max_slots=max([p.info.slots for p in self.preps] + [4]),
             max_words=max([p.info.W for p in self.preps] + [1]),
-            reserved=0,
+            max_kp=max([max(p.k, 7) for p in self.preps] + [7]),
             d_tables=self.tables.data_ptr(), d_offsets=self.offsets.data_ptr())
         self.table_bytes = total * 4
 
@@ -184,18 +184,19 @@ class DeviceBatch:
 
 
 def build_queue(k: np.ndarray, cbits: int, lanes: int, cost: Optional[np.ndarray] = None,
-                max_items_per_instance: int = 0, order: int = 0) -> np.ndarray:
+                max_items_per_instance: int = 0, order: int = 0,
+                min_items_per_instance: int = 1) -> np.ndarray:
     lib = L.lib()
     ka = np.ascontiguousarray(k, dtype=np.int32)
     ca = None if cost is None else np.ascontiguousarray(cost, dtype=np.float32)
     n = ctypes.c_int64(0)
     cp = None if ca is None else _ptr(ca, L.c_f32p)
-    st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, len(ka), cbits, lanes, max_items_per_instance,
-                             order, None, 0, ctypes.byref(n))
+    st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, len(ka), cbits, lanes, min_items_per_instance,
+                             max_items_per_instance, order, None, 0, ctypes.byref(n))
     L.check("wpm_build_queue", st, (L.WPM_ECAP, L.WPM_OK))
     items = (L.Item * max(1, n.value))()
-    st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, len(ka), cbits, lanes, max_items_per_instance,
-                             order, items, n.value, ctypes.byref(n))
+    st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, len(ka), cbits, lanes, min_items_per_instance,
+                             max_items_per_instance, order, items, n.value, ctypes.byref(n))
     L.check("wpm_build_queue", st)
     arr = np.frombuffer(items, dtype=np.dtype([("instance", "<u4"), ("cbits", "<u2"),
                                                ("lanes", "<u2"), ("first", "<u8")]),
@@ -254,6 +255,18 @@ class Sweeper:
                                    ctypes.c_void_p(stream.cuda_stream))
         L.check("wpm_enumerate", st)
 
+    def fetch_records(self, n: int):
+        """Copy the first n survivor records {x, instance} into a pinned host
+        buffer (allocated once) and return a numpy view of them."""
+        torch = self.torch
+        n = min(int(n), self.cap)
+        if getattr(self, "_pinned", None) is None or self._pinned.shape[0] < n:
+            self._pinned = torch.empty((max(n, 1), 2), dtype=torch.int64, pin_memory=True)
+        if n:
+            self._pinned[:n].copy_(self.surv[:n], non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        return self._pinned[:n].numpy()
+
     def result(self) -> SweepResult:
         self.torch.cuda.synchronize()
         counts = self.counts[:len(self.batch.preps)].cpu().numpy().astype(np.uint64)
@@ -308,12 +321,13 @@ class Sweeper:
 def sweep(preps: Sequence[Prepared], mode: int = L.SCHED_DYNAMIC, cbits: int = 12,
           wg_size: int = 256, grid: int = 0, cap: int = 1 << 20, order: int = 0,
           cost: Optional[np.ndarray] = None, max_items_per_instance: int = 0,
-          want_sets: bool = True):
+          min_items_per_instance: int = 1, want_sets: bool = True):
     """Convenience: upload, sweep, collect.  Returns (SweepResult, sets or None)."""
     batch = DeviceBatch(preps)
     sw = Sweeper(batch, cap=cap)
     items = build_queue(batch.k, cbits, wg_size, cost=cost,
-                        max_items_per_instance=max_items_per_instance, order=order)
+                        max_items_per_instance=max_items_per_instance, order=order,
+                        min_items_per_instance=min_items_per_instance)
     sw.set_items(items)
     sw.launch(mode, wg_size=wg_size, grid=grid)
     res = sw.result()
