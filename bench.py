@@ -92,8 +92,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--instances", type=int, default=16384)
-    ap.add_argument("--cbits", type=int, default=16)
-    ap.add_argument("--wg", type=int, default=256)
+    ap.add_argument("--cbits", type=int, default=0, help="lane chunk bits (0 = autotuned)")
+    ap.add_argument("--wg", type=int, default=0, help="workgroup size (0 = autotuned)")
     ap.add_argument("--max-items", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-static", action="store_true")
@@ -101,6 +101,11 @@ def main():
     ap.add_argument("--plain-min-items", type=int, default=512,
                     help="plain schedule: split each instance over at least this many workgroups")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--train-instances", type=int, default=4096)
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--learned-policy", default="dynamic", choices=["packed", "dynamic"])
+    ap.add_argument("--no-split", action="store_true",
+                    help="one launch under the largest kernel template instead of one per class")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for counter calibration)")
@@ -122,56 +127,98 @@ def main():
     vectors = batch.vectors
     log(f"sum 2^k = {vectors:.4e}; tables {batch.table_bytes / 1e6:.1f} MB in HBM")
     stream = torch.cuda.current_stream()
+    tuned = None
+    if args.cbits == 0 or args.wg == 0:
+        from paper_2301_00806_amd import tune as T
+        tuned = T.tune(preps, log=log)
+        log(f"autotuner ({'cached' if tuned['cached'] else 'measured'}, {tuned['key']}): "
+            f"cbits={tuned['cbits']} wg={tuned['wg']}")
+        args.cbits = args.cbits or tuned["cbits"]
+        args.wg = args.wg or tuned["wg"]
     sw = E.Sweeper(batch, cap=args.cap)
-    k = batch.k
 
-    def make_items(order_cost, min_items=1):
-        return E.build_queue(k, args.cbits, args.wg, cost=order_cost,
-                             max_items_per_instance=args.max_items,
-                             order=1 if order_cost is not None else 0,
-                             min_items_per_instance=min_items)
+    # ---- learned part: labels from timed sweeps of the batch workload, MLP
+    # trained on the GPU by the engine's own forward/backward/Adam kernels
+    from paper_2301_00806_amd import costmodel as CM
+    from paper_2301_00806_amd import scheduler as S
+    t = time.time()
+    import wpm_inputs as W
+    train_insts = W.batch(E.kdim, count=args.train_instances)
+    train_preps = E.prepare_many(train_insts)
+    Xtr, Ttr, _ = S.measure_labels(train_preps, cbits=12, wg=args.wg)
+    model = CM.CostModel(seed=0)
+    model.fit(Xtr, Ttr, epochs=args.epochs, lr=3e-3, batch=512)
+    train_loss = model.loss(Xtr, Ttr)
+    log(f"cost model trained on {len(Xtr)} instances in {time.time() - t:.1f}s, loss {train_loss:.4f}")
 
-    def timed(mode, items, steps, warmup, label):
-        sw.set_items(items)
+    feats = CM.features_of(preps)
+
+    def plan_learned():
+        cost = S.per_vector_cost(model, feats)       # MLP inference on the GPU
+        return S.make_plan(batch, args.learned_policy, cost=cost, cbits=args.cbits, wg=args.wg,
+                           split=not args.no_split)
+
+    def timed_plan(make, steps, warmup, label):
+        plan = make()
         for _ in range(warmup):
-            sw.launch(mode, wg_size=args.wg, stream=stream)
+            sw.set_items(plan.items, segments=plan.segments)
+            sw.launch(plan.mode, wg_size=args.wg, stream=stream)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         kern_ms = []
         t0 = time.perf_counter()
         for _ in range(steps):
+            plan = make()                              # scheduling is part of the step
+            sw.set_items(plan.items, segments=plan.segments)
             e0.record(stream)
-            sw.launch(mode, wg_size=args.wg, stream=stream)
+            sw.launch(plan.mode, wg_size=args.wg, stream=stream)
             e1.record(stream)
             counts = sw.counts[:len(preps)].cpu()      # synchronises the stream
-            tot = int(sw.total.item())
-            if tot > sw.cap:
-                raise SystemExit(f"survivor buffer too small: {tot} > {sw.cap}")
-            rec = sw.fetch_records(tot)                # survivor records to pinned host memory
+            tot, slots = (int(v) for v in sw.total.cpu())
+            if slots > sw.cap:
+                raise SystemExit(f"survivor buffer too small: {slots} > {sw.cap}")
+            rec = sw.fetch_records(slots)              # survivor records to pinned host memory
             kern_ms.append(e0.elapsed_time(e1))
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
         res = sw.result()
         log(f"{label}: kernel {np.mean(kern_ms):.2f} ms, step {wall * 1e3:.2f} ms, "
-            f"{vectors / (wall):.3e} vectors/s, total WPMs {res.total}, stats {res.stats[:3]}")
+            f"{vectors / wall:.3e} vectors/s, total WPMs {res.total}, stats {res.stats[:3]}")
         return wall, float(np.mean(kern_ms)), res
 
-    # batched: persistent launch, items in descending predicted cost (2^k x per-vector cost)
-    cost = np.ones(len(preps), dtype=np.float32)
-    items_b = make_items(cost)
-    t_b, k_b, res_b = timed(L.SCHED_DYNAMIC, items_b, args.steps, args.warmup, "batched")
+    t_b, k_b, res_b = timed_plan(plan_learned, args.steps, args.warmup, f"learned-{args.learned_policy}")
     out = {}
+    sp = not args.no_split
+    others = [("static", lambda: S.make_plan(batch, "static", cbits=args.cbits, wg=args.wg, split=sp)),
+              ("dynamic_pow2", lambda: S.make_plan(batch, "dynamic", cbits=args.cbits, wg=args.wg, split=sp)),
+              ("packed_pow2", lambda: S.make_plan(batch, "packed", cbits=args.cbits, wg=args.wg, split=sp))]
     if not args.no_plain:
-        items_p = make_items(None, min_items=args.plain_min_items)
-        t_p, k_p, res_p = timed(L.SCHED_PLAIN, items_p, max(1, args.steps // 2), 1, "plain")
-        assert np.array_equal(res_p.counts, res_b.counts), "plain and batched counts differ"
-        out["plain"] = {"value": vectors / t_p, "ms_per_step": t_p * 1e3, "kernel_ms": k_p}
-    if not args.no_static:
-        items_s = make_items(None)
-        t_s, k_s, res_s = timed(L.SCHED_STATIC, items_s, max(1, args.steps // 2), 1, "batched-static")
-        assert np.array_equal(res_s.counts, res_b.counts), "static and batched counts differ"
-        out["batched_static"] = {"value": vectors / t_s, "ms_per_step": t_s * 1e3, "kernel_ms": k_s}
+        others.append(("plain", lambda: S.make_plan(batch, "plain", cbits=args.cbits, wg=args.wg,
+                                                    plain_min_items=args.plain_min_items, split=sp)))
+    other_pol = "packed" if args.learned_policy == "dynamic" else "dynamic"
+    others.append((f"{other_pol}_model", lambda: S.make_plan(
+        batch, other_pol, cost=S.per_vector_cost(model, feats), cbits=args.cbits, wg=args.wg, split=sp)))
+    for name, mk in others:
+        if args.no_static and name == "static":
+            continue
+        st = max(1, args.steps // 2) if name != "plain" else 1
+        t_o, k_o, res_o = timed_plan(mk, st, 1, name)
+        assert np.array_equal(res_o.counts, res_b.counts), f"{name} counts differ"
+        out[name] = {"value": vectors / t_o, "ms_per_step": t_o * 1e3, "kernel_ms": k_o}
+
+    # model error on the fresh instances: measured per-instance time vs prediction
+    _, Tte, _ = S.measure_labels(preps, cbits=args.cbits, wg=args.wg, repeats=1)
+    pred = model.predict(feats)
+    ok = np.isfinite(Tte[:, 0])
+    err = pred[ok, 0] - Tte[ok, 0]
+    base = np.median(Ttr[:, 0]) - Tte[ok, 0]       # "cost proportional to 2^k": constant ns/vector
+    model_err = {"log_rmse": float(np.sqrt(np.mean(err ** 2))),
+                 "mape": float(np.mean(np.abs(np.expm1(err)))),
+                 "log_rmse_pow2_heuristic": float(np.sqrt(np.mean(base ** 2))),
+                 "mape_pow2_heuristic": float(np.mean(np.abs(np.expm1(base)))),
+                 "train_instances": len(Xtr), "train_loss": train_loss}
+    log(f"model error on fresh instances: {model_err}")
 
     if args.copy_calibration:
         a = torch.empty(1 << 26, dtype=torch.int32, device="cuda")
@@ -197,11 +244,15 @@ def main():
         "config": {"workload": "learned-scheduler batch: 16384 lambda = [I_n | 4 uniform], "
                                "n = 5..8, m = n + 4, k <= 36",
                    "instances": len(preps), "sum_2k": vectors, "cbits": args.cbits,
-                   "wg_size": args.wg, "schedule": "persistent dynamic queue, LPT order"},
+                   "wg_size": args.wg,
+                   "schedule": f"learned: {args.learned_policy}, LPT on MLP-predicted cost"},
         "wpm_total": int(res_b.total),
         "wpm_counts_sha256": __import__("hashlib").sha256(res_b.counts.tobytes()).hexdigest(),
         "kernel_ms": k_b,
         "schedules": out,
+        "cost_model": model_err,
+        "autotune": None if tuned is None else {"key": tuned["key"], "cbits": tuned["cbits"],
+                                                "wg": tuned["wg"], "cached": tuned["cached"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": INT32_PEAK / 1e12,
                      "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved / (INT32_PEAK / 1e12),
                      "traffic": None,

@@ -62,7 +62,7 @@ enum {
 #define WPM_MAX_GROUPS 16   /* 32-ridge groups of critical ridges (<= 512 ridges) */
 #define WPM_MAX_SLOTS 8     /* parents-1 of a critical ridge */
 #define WPM_LOW_BITS 6      /* Gray steps unrolled per block: 2^6 */
-#define WPM_TABLE_ROWS 128  /* low-part rows staged per instance: 2 * 2^6 */
+#define WPM_TABLE_ROWS 64   /* low-part rows staged per instance: 2^6 */
 
 /* Human-readable text of a status code (static storage). */
 const char *wpm_strerror(int status);
@@ -156,7 +156,8 @@ typedef struct wpm_item {
 enum {
     WPM_SCHED_PLAIN = 0,   /* one launch per instance over its own items */
     WPM_SCHED_STATIC = 1,  /* one persistent launch, workgroup g takes items g, g+G, ... */
-    WPM_SCHED_DYNAMIC = 2  /* one persistent launch, items popped from a device queue */
+    WPM_SCHED_DYNAMIC = 2, /* one persistent launch, items popped from a device queue */
+    WPM_SCHED_PACKED = 3   /* one launch, workgroup g runs bin g of a host-packed assignment */
 };
 
 /*
@@ -172,11 +173,23 @@ enum {
  *   max_items_per_instance  > 0: coarsen chunks so an instance yields at most
  *                    this many items (raises cbits; applied after the minimum)
  *   order            0 = instance order, 1 = descending item cost (LPT)
+ *   Instances with k = 0 yield no items (their only vector is x = 0).
  *   items, cap       output (host); *n_out = item count (WPM_ECAP if > cap)
  */
 int wpm_build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits,
                     int32_t lanes, int32_t min_items_per_instance, int32_t max_items_per_instance,
                     int32_t order, wpm_item *items, int64_t cap, int64_t *n_out);
+
+/*
+ * Pack items into `bins` workgroup bins by longest-processing-time-first:
+ * items in decreasing cost (cost[instance] * lanes * 2^cbits, cost NULL =
+ * 1.0) each go to the bin with the least total so far (ties: lowest bin).
+ *   items[n], out_items[n]   out_items lists the items bin by bin
+ *   out_offsets[bins + 1]    bin b holds out_items[out_offsets[b] .. out_offsets[b+1])
+ *   max_load                 optional: receives the largest bin total
+ */
+int wpm_pack_bins(const wpm_item *items, int64_t n, const float *cost, int32_t bins,
+                  wpm_item *out_items, int64_t *out_offsets, double *max_load);
 
 /* Device-resident batch. */
 typedef struct wpm_batch {
@@ -190,26 +203,38 @@ typedef struct wpm_batch {
     const int64_t *d_offsets;  /* device: word offset of each table in d_tables */
 } wpm_batch;
 
+#define WPM_FLAG_ACCUMULATE 1 /* do not clear d_counts, d_total, d_stats: add to them */
+
 typedef struct wpm_sched {
     int32_t mode;              /* WPM_SCHED_* */
-    int32_t wg_size;           /* threads per workgroup: 64, 128, 256, 512 or 1024 */
-    int32_t grid;              /* persistent modes: workgroups (0 = 4 per CU) */
-    int32_t reserved;
+    int32_t wg_size;           /* threads per workgroup: 64, 128, 256 or 512 */
+    int32_t grid;              /* persistent modes: workgroups (0 = occupancy x CUs) */
+    int32_t flags;             /* WPM_FLAG_* */
     const wpm_item *d_items;   /* device: the items */
     const wpm_item *h_items;   /* host copy (PLAIN mode launches per instance from it) */
     int64_t num_items;
     uint32_t *d_scratch;       /* device: >= 4 words (queue head), cleared by the call */
     uint64_t *d_item_times;    /* optional device [num_items][2]: start, end (s_memrealtime) */
+    const int64_t *d_bin_offsets; /* PACKED mode: device [grid + 1] from wpm_pack_bins */
 } wpm_sched;
+
+/* Workgroups a persistent launch of this batch uses by default: the
+ * occupancy of the selected kernel instantiation times the compute units. */
+int wpm_persistent_grid(const wpm_batch *batch, int32_t wg_size, int32_t *grid);
 
 /*
  * Sweep every item on `stream`.
- *   d_survivors [cap][2] uint64 device records {x, instance}; only the first
- *               cap survivors are written, in no particular order
+ *   d_survivors [cap][2] uint64 device records {x, instance}.  Waves reserve
+ *               record slots in chunks, so the slots used may exceed the
+ *               results; unused slots hold the sentinel {0, ~0}.  Records are
+ *               in no particular order; slots at or beyond cap are not written.
  *   d_counts    [num_instances] uint64 device; set to each instance's exact
- *               number of results (cleared by the call)
- *   d_total     [1] uint64 device; total results (> cap: the caller needs a
- *               larger buffer; wpm_collect returns WPM_ECAP)
+ *               number of results (cleared by the call unless
+ *               WPM_FLAG_ACCUMULATE: then a batch can be swept by several calls,
+ *               for example one per kernel template class, into one set of counts)
+ *   d_total     [2] uint64 device: [0] total results, [1] record slots used
+ *               ([1] > cap: the caller needs a larger buffer and wpm_collect
+ *               returns WPM_ECAP; counts stay exact)
  *   d_stats     optional [8] uint64 device counters: [0] filter fires (wave
  *               steps with a lane passing the fast filter), [1] lanes passing
  *               every ridge check, [2] vectors rejected by the upper bound
@@ -248,6 +273,43 @@ int wpm_collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_s
                 uint64_t cap, const uint64_t *d_counts, const uint64_t *d_total,
                 uint64_t *h_counts, uint32_t *h_out, int64_t out_cap, int64_t *out_words,
                 int64_t *h_offsets, void *stream);
+
+/* ------------------------------------------------------------ cost model */
+
+/*
+ * Learned cost model for the persistent scheduler: an MLP 16 -> 64 -> 64 -> 2
+ * in fp32 with ReLU hidden layers, mapping the 16 features of
+ * wpm_instance_info.features to [natural log of sweep time per kernel vector
+ * in ns, log10 of the survivor density].  It orders and sizes work items
+ * only; it never removes any vector from the sweep.
+ * Parameters (device, WPM_MLP_PARAMS floats): W1[64][16] b1[64] W2[64][64]
+ * b2[64] W3[2][64] b3[2] (row-major, W[out][in]).  Normalisation (device,
+ * WPM_MLP_NORM floats): mean_x[16] std_x[16] mean_y[2] std_y[2]; inputs are
+ * standardised and outputs de-standardised inside the kernels.
+ */
+#define WPM_MLP_IN 16
+#define WPM_MLP_HIDDEN 64
+#define WPM_MLP_OUT 2
+#define WPM_MLP_PARAMS 5378
+#define WPM_MLP_NORM 36
+
+/* Floats of device work space wpm_mlp_grad needs for `batch` samples. */
+int64_t wpm_mlp_work_floats(int32_t batch);
+
+/* d_y[batch][2] = model(d_x[batch][16]) on `stream`. */
+int wpm_mlp_forward(const float *d_params, const float *d_norm, const float *d_x, int32_t batch,
+                    float *d_y, void *stream);
+
+/* Gradient of the mean squared error on standardised targets d_t[batch][2]
+ * into d_grad[WPM_MLP_PARAMS] (a fixed-order sum: bitwise reproducible);
+ * d_loss[1] (optional) receives the loss.  d_work: wpm_mlp_work_floats(batch). */
+int wpm_mlp_grad(const float *d_params, const float *d_norm, const float *d_x, const float *d_t,
+                 int32_t batch, float *d_grad, float *d_work, float *d_loss, void *stream);
+
+/* One Adam step (Kingma and Ba) with bias correction for step >= 1 and
+ * an L2 term weight_decay * param added to the gradient. */
+int wpm_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t step,
+                 float lr, float beta1, float beta2, float eps, float weight_decay, void *stream);
 
 #ifdef __cplusplus
 }

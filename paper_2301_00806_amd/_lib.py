@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwpm.so")
 
 WPM_OK, WPM_EINVAL, WPM_ECAP, WPM_EKMAX, WPM_EHIP, WPM_ELIMIT = 0, -1, -2, -3, -4, -5
-SCHED_PLAIN, SCHED_STATIC, SCHED_DYNAMIC = 0, 1, 2
+SCHED_PLAIN, SCHED_STATIC, SCHED_DYNAMIC, SCHED_PACKED = 0, 1, 2, 3
+FLAG_ACCUMULATE = 1
 MAX_K = 64
 
 c_u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -43,9 +44,10 @@ class Batch(ctypes.Structure):
 
 class Sched(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("wg_size", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("d_items", ctypes.c_void_p),
+                ("flags", ctypes.c_int32), ("d_items", ctypes.c_void_p),
                 ("h_items", ctypes.c_void_p), ("num_items", ctypes.c_int64),
-                ("d_scratch", ctypes.c_void_p), ("d_item_times", ctypes.c_void_p)]
+                ("d_scratch", ctypes.c_void_p), ("d_item_times", ctypes.c_void_p),
+                ("d_bin_offsets", ctypes.c_void_p)]
 
 
 class HostInstance(ctypes.Structure):
@@ -74,6 +76,12 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
                           "or python paper_2301_00806_amd/build.py")
+    # PyTorch supplies the process's HIP runtime: torch's bundled
+    # libamdhip64 carries the soname libamdhip64.so.7, so once torch is loaded
+    # libwpm.so binds to that same runtime (one runtime, shared streams and
+    # device memory).  Loading libwpm.so first would bring in a second HIP
+    # runtime from /opt/rocm and torch would then find no devices.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     L.wpm_strerror.restype = ctypes.c_char_p
     L.wpm_strerror.argtypes = [ctypes.c_int]
@@ -94,16 +102,31 @@ def lib():
     L.wpm_build_queue.argtypes = [c_i32p, c_f32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Item),
                                   ctypes.c_int64, c_i64p]
+    L.wpm_pack_bins.restype = ctypes.c_int
+    L.wpm_pack_bins.argtypes = [ctypes.POINTER(Item), ctypes.c_int64, c_f32p, ctypes.c_int32,
+                                ctypes.POINTER(Item), c_i64p, ctypes.POINTER(ctypes.c_double)]
     L.wpm_enumerate.restype = ctypes.c_int
     L.wpm_enumerate.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Sched), ctypes.c_void_p,
                                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p]
+    L.wpm_persistent_grid.restype = ctypes.c_int
+    L.wpm_persistent_grid.argtypes = [ctypes.POINTER(Batch), ctypes.c_int32, c_i32p]
     L.wpm_device_query.restype = ctypes.c_int
     L.wpm_device_query.argtypes = [c_i32p, c_i64p, c_i32p]
     L.wpm_collect.restype = ctypes.c_int
     L.wpm_collect.argtypes = [ctypes.POINTER(HostInstance), ctypes.c_int32, ctypes.c_void_p,
                               ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, c_u64p,
                               c_u32p, ctypes.c_int64, c_i64p, c_i64p, ctypes.c_void_p]
+    vp = ctypes.c_void_p
+    L.wpm_mlp_work_floats.restype = ctypes.c_int64
+    L.wpm_mlp_work_floats.argtypes = [ctypes.c_int32]
+    L.wpm_mlp_forward.restype = ctypes.c_int
+    L.wpm_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp]
+    L.wpm_mlp_grad.restype = ctypes.c_int
+    L.wpm_mlp_grad.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp]
+    L.wpm_mlp_adam.restype = ctypes.c_int
+    L.wpm_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
     _lib = L
     return L
 
@@ -116,5 +139,7 @@ def check(call: str, status: int, ok=(WPM_OK,)) -> int:
 
 # Every symbol include/wpm.h declares.
 EXPORTED = ("wpm_strerror", "wpm_last_hip_error", "wpm_build_candidates", "wpm_kernel_basis",
-            "wpm_ubt_bound", "wpm_pack_instance", "wpm_build_queue", "wpm_enumerate",
-            "wpm_device_query", "wpm_collect")
+            "wpm_ubt_bound", "wpm_pack_instance", "wpm_build_queue", "wpm_pack_bins", "wpm_enumerate",
+            "wpm_device_query", "wpm_persistent_grid", "wpm_collect", "wpm_mlp_work_floats", "wpm_mlp_forward",
+            "wpm_mlp_grad", "wpm_mlp_adam")
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS, MLP_NORM = 16, 64, 2, 5378, 36

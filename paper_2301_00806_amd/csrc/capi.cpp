@@ -8,7 +8,15 @@ int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv,
             const uint64_t *d_counts, const uint64_t *d_total, uint64_t *h_counts, uint32_t *h_out,
             int64_t out_cap, int64_t *out_words, int64_t *h_offsets, void *stream);
 int device_query(int32_t *num_cus, int64_t *wallclock_khz, int32_t *lds_per_block);
+int persistent_grid(const wpm_batch *b, int wg_size, int32_t *grid);
 const char *last_hip_error();
+int64_t mlp_work_floats(int B);
+int mlp_forward_launch(const float *params, const float *norm, const float *X, int B, float *Y,
+                       void *stream);
+int mlp_grad_launch(const float *params, const float *norm, const float *X, const float *T, int B,
+                    float *grad, float *work, float *loss, void *stream);
+int mlp_adam_launch(float *params, const float *grad, float *m, float *v, int step, float lr,
+                    float beta1, float beta2, float eps, float weight_decay, void *stream);
 }  // namespace wpm
 
 extern "C" {
@@ -53,10 +61,19 @@ int wpm_build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cb
                             max_items_per_instance, order, items, cap, n_out);
 }
 
+int wpm_pack_bins(const wpm_item *items, int64_t n, const float *cost, int32_t bins,
+                  wpm_item *out_items, int64_t *out_offsets, double *max_load) {
+    return wpm::pack_bins(items, n, cost, bins, out_items, out_offsets, max_load);
+}
+
 int wpm_enumerate(const wpm_batch *batch, const wpm_sched *sched, uint64_t *d_survivors,
                   uint64_t cap, uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats,
                   void *stream) {
     return wpm::enumerate(batch, sched, d_survivors, cap, d_counts, d_total, d_stats, stream);
+}
+
+int wpm_persistent_grid(const wpm_batch *batch, int32_t wg_size, int32_t *grid) {
+    return wpm::persistent_grid(batch, wg_size, grid);
 }
 
 int wpm_device_query(int32_t *num_cus, int64_t *wallclock_khz, int32_t *lds_per_block) {
@@ -69,6 +86,24 @@ int wpm_collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_s
                 int64_t *h_offsets, void *stream) {
     return wpm::collect(insts, num, d_survivors, cap, d_counts, d_total, h_counts, h_out, out_cap,
                         out_words, h_offsets, stream);
+}
+
+int64_t wpm_mlp_work_floats(int32_t batch) { return wpm::mlp_work_floats(batch); }
+
+int wpm_mlp_forward(const float *d_params, const float *d_norm, const float *d_x, int32_t batch,
+                    float *d_y, void *stream) {
+    return wpm::mlp_forward_launch(d_params, d_norm, d_x, batch, d_y, stream);
+}
+
+int wpm_mlp_grad(const float *d_params, const float *d_norm, const float *d_x, const float *d_t,
+                 int32_t batch, float *d_grad, float *d_work, float *d_loss, void *stream) {
+    return wpm::mlp_grad_launch(d_params, d_norm, d_x, d_t, batch, d_grad, d_work, d_loss, stream);
+}
+
+int wpm_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t step,
+                 float lr, float beta1, float beta2, float eps, float weight_decay, void *stream) {
+    return wpm::mlp_adam_launch(d_params, d_grad, d_m, d_v, step, lr, beta1, beta2, eps,
+                                weight_decay, stream);
 }
 
 }  // extern "C"

@@ -88,6 +88,22 @@ int device_query(int32_t *num_cus, int64_t *wallclock_khz, int32_t *lds_per_bloc
     return WPM_OK;
 }
 
+int persistent_grid(const wpm_batch *b, int wg_size, int32_t *grid) {
+    if (!b || !grid || wg_size < 64 || wg_size > 512 || (wg_size % 64)) return WPM_EINVAL;
+    if (b->max_groups < 1 || b->max_groups > WPM_MAX_GROUPS) return WPM_EINVAL;
+    if (b->max_slots != 4 && b->max_slots != 8) return WPM_EINVAL;
+    const int gm = pick_gm(b->max_groups), qs = b->max_slots, wm = pick_wm(b->max_words);
+    const size_t lds =
+        (size_t)(WPM_TABLE_ROWS + b->max_kp) * (size_t)b->max_row_words * sizeof(uint32_t);
+    int32_t cus = 0;
+    int rc = device_query(&cus, nullptr, nullptr);
+    if (rc) return rc;
+    int nb = 0;
+    HIP_TRY(occupancy(gm, qs, wm, &nb, wg_size, lds));
+    *grid = std::max(1, nb) * cus;
+    return WPM_OK;
+}
+
 int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t cap,
               uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats, void *stream) {
     if (!b || !s || !d_counts || !d_total || (cap > 0 && !d_surv)) return WPM_EINVAL;
@@ -96,9 +112,10 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     if (b->max_slots != 4 && b->max_slots != 8) return WPM_EINVAL;
     if (b->max_words < 0 || b->max_words > 32 || b->max_row_words < 4) return WPM_EINVAL;
     if (b->max_kp < 7 || b->max_kp > WPM_MAX_K) return WPM_EINVAL;
-    if (s->wg_size < 64 || s->wg_size > 1024 || (s->wg_size % 64)) return WPM_EINVAL;
+    if (s->wg_size < 64 || s->wg_size > 512 || (s->wg_size % 64)) return WPM_EINVAL;
     if (s->num_items < 0 || (s->num_items > 0 && !s->d_items)) return WPM_EINVAL;
-    if (s->mode < WPM_SCHED_PLAIN || s->mode > WPM_SCHED_DYNAMIC) return WPM_EINVAL;
+    if (s->mode < WPM_SCHED_PLAIN || s->mode > WPM_SCHED_PACKED) return WPM_EINVAL;
+    if (s->mode == WPM_SCHED_PACKED && (!s->d_bin_offsets || s->grid < 1)) return WPM_EINVAL;
     if (s->mode == WPM_SCHED_PLAIN && s->num_items > 0 && !s->h_items) return WPM_EINVAL;
     if (s->mode == WPM_SCHED_DYNAMIC && !s->d_scratch) return WPM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
@@ -106,14 +123,17 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     const size_t lds =
         (size_t)(WPM_TABLE_ROWS + b->max_kp) * (size_t)b->max_row_words * sizeof(uint32_t);
     int32_t lds_max = 0;
+    if (cap >= (UINT64_MAX >> 2)) return WPM_EINVAL;
     int rc = device_query(nullptr, nullptr, &lds_max);
     if (rc) return rc;
     if (lds > (size_t)lds_max) return WPM_ELIMIT;
 
     int st_rc;
-    if ((st_rc = zero(d_counts, b->num_instances, st))) return st_rc;
-    if ((st_rc = zero(d_total, 1, st))) return st_rc;
-    if ((st_rc = zero(d_stats, 8, st))) return st_rc;
+    if (!(s->flags & WPM_FLAG_ACCUMULATE)) {
+        if ((st_rc = zero(d_counts, b->num_instances, st))) return st_rc;
+        if ((st_rc = zero(d_total, 2, st))) return st_rc;
+        if ((st_rc = zero(d_stats, 8, st))) return st_rc;
+    }
     if (s->d_scratch && (st_rc = zero(s->d_scratch, 2, st))) return st_rc;
     if (s->num_items == 0) return WPM_OK;
 
@@ -125,8 +145,10 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     a.cap = cap;
     a.counts = (unsigned long long *)d_counts;
     a.total = (unsigned long long *)d_total;
+    a.slots = (unsigned long long *)d_total + 1;
     a.stats = (unsigned long long *)d_stats;
     a.times = s->d_item_times;
+    a.bins = s->d_bin_offsets;
     const dim3 block((unsigned)s->wg_size);
     if (s->mode == WPM_SCHED_PLAIN) {
         // One launch per instance: a grid of exactly that instance's items.
@@ -145,15 +167,9 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
         }
         return WPM_OK;
     }
-    int grid = s->grid;
-    if (grid <= 0) {
-        int32_t cus = 0;
-        if ((rc = device_query(&cus, nullptr, nullptr))) return rc;
-        int nb = 0;
-        HIP_TRY(occupancy(gm, qs, wm, &nb, s->wg_size, lds));
-        grid = std::max(1, nb) * cus;
-    }
-    a.mode = (s->mode == WPM_SCHED_STATIC) ? 1 : 2;
+    int32_t grid = s->grid;
+    if (grid <= 0 && (rc = persistent_grid(b, s->wg_size, &grid))) return rc;
+    a.mode = (s->mode == WPM_SCHED_STATIC) ? 1 : (s->mode == WPM_SCHED_DYNAMIC) ? 2 : 3;
     HIP_TRY(launch(gm, qs, wm, dim3((unsigned)grid), block, lds, st, b->d_tables, b->d_offsets,
                    s->d_items, a));
     return WPM_OK;
@@ -166,30 +182,34 @@ int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv,
         (num > 0 && !insts))
         return WPM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    uint64_t total = 0;
+    uint64_t tot[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(h_counts, d_counts, sizeof(uint64_t) * (size_t)num, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(&total, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(tot, d_total, sizeof(tot), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    const uint64_t got = std::min(total, cap);
-    std::vector<uint64_t> rec(2 * got);
-    if (got) {
-        HIP_TRY(hipMemcpyAsync(rec.data(), d_surv, sizeof(uint64_t) * 2 * got, hipMemcpyDeviceToHost, st));
+    const uint64_t total = tot[0], slots = tot[1];
+    if (slots > cap) {
+        *out_words = -(int64_t)slots;  // record slots needed
+        return WPM_ECAP;
+    }
+    std::vector<uint64_t> rec(2 * slots);
+    if (slots) {
+        HIP_TRY(hipMemcpyAsync(rec.data(), d_surv, sizeof(uint64_t) * 2 * slots, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
     uint64_t sum = 0;
     for (int i = 0; i < num; ++i) sum += h_counts[i];
-    if (total > cap) {
-        *out_words = -1;
-        return WPM_ECAP;
-    }
-    if (sum != total) return WPM_EINVAL;  // counts and records disagree: corrupted buffers
+    if (sum != total) return WPM_EINVAL;  // counts and total disagree: corrupted buffers
     // group by instance, expand x -> facet list, canonical order
     std::vector<std::vector<uint64_t>> per(num);
-    for (uint64_t r = 0; r < got; ++r) {
+    uint64_t found = 0;
+    for (uint64_t r = 0; r < slots; ++r) {
         const uint64_t inst = rec[2 * r + 1];
+        if (inst == ~0ull) continue;  // unused slot of a wave's chunk
         if (inst >= (uint64_t)num) return WPM_EINVAL;
         per[inst].push_back(rec[2 * r]);
+        ++found;
     }
+    if (found != total) return WPM_EINVAL;
     int64_t words = 0;
     std::vector<std::vector<std::vector<uint32_t>>> res(num);
     for (int i = 0; i < num; ++i) {

@@ -53,6 +53,9 @@ int build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits,
                 int32_t min_items_per_instance, int32_t max_items_per_instance, int32_t order,
                 wpm_item *items, int64_t cap, int64_t *n_out);
 
+int pack_bins(const wpm_item *items, int64_t n, const float *cost, int32_t bins,
+              wpm_item *out_items, int64_t *out_offsets, double *max_load);
+
 void set_hip_error(const char *what, int code, const char *text);
 
 }  // namespace wpm

@@ -29,6 +29,9 @@ int build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits,
     int64_t total = 0;
     for (int i = 0; i < num; ++i) {
         if (k[i] < 0 || k[i] > WPM_MAX_K) return WPM_EINVAL;
+        // k = 0: the only kernel vector is x = 0, the empty complex, which is
+        // never a result; the instance needs no sweep.
+        if (k[i] == 0) continue;
         const int kp = std::max(k[i], 7);
         int c = std::min(std::max(cbits, 7), kp);
         auto n_items = [&](int cc) -> uint64_t {
@@ -66,6 +69,45 @@ int build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits,
         std::stable_sort(out.begin(), out.end(),
                          [](const Tmp &a, const Tmp &b) { return a.cost > b.cost; });
     for (size_t i = 0; i < out.size(); ++i) items[i] = out[i].it;
+    return WPM_OK;
+}
+
+int pack_bins(const wpm_item *items, int64_t n, const float *cost, int32_t bins,
+              wpm_item *out_items, int64_t *out_offsets, double *max_load) {
+    if (n < 0 || bins < 1 || (n > 0 && (!items || !out_items)) || !out_offsets) return WPM_EINVAL;
+    std::vector<double> c(n);
+    for (int64_t i = 0; i < n; ++i)
+        c[i] = (cost ? (double)cost[items[i].instance] : 1.0) * (double)items[i].lanes *
+               std::ldexp(1.0, items[i].cbits);
+    std::vector<int64_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return c[a] > c[b]; });
+    // min-heap of (load, bin)
+    std::vector<std::pair<double, int32_t>> heap(bins);
+    for (int32_t b = 0; b < bins; ++b) heap[b] = {0.0, b};
+    auto cmp = [](const std::pair<double, int32_t> &a, const std::pair<double, int32_t> &b) {
+        return a.first > b.first || (a.first == b.first && a.second > b.second);
+    };
+    std::make_heap(heap.begin(), heap.end(), cmp);
+    std::vector<int32_t> bin_of(n);
+    std::vector<int64_t> cnt(bins, 0);
+    for (int64_t i : order) {
+        std::pop_heap(heap.begin(), heap.end(), cmp);
+        auto &top = heap.back();
+        bin_of[i] = top.second;
+        top.first += c[i];
+        ++cnt[top.second];
+        std::push_heap(heap.begin(), heap.end(), cmp);
+    }
+    out_offsets[0] = 0;
+    for (int32_t b = 0; b < bins; ++b) out_offsets[b + 1] = out_offsets[b] + cnt[b];
+    std::vector<int64_t> fill(out_offsets, out_offsets + bins);
+    for (int64_t i : order) out_items[fill[bin_of[i]]++] = items[i];  // costly items first in each bin
+    if (max_load) {
+        double mx = 0;
+        for (auto &h : heap) mx = std::max(mx, h.first);
+        *max_load = mx;
+    }
     return WPM_OK;
 }
 

@@ -16,13 +16,14 @@
 //            updated by 4 XORs and tested by 3 bit-logic ops per step;
 //            the steps where some lane passes are recorded in a 64-bit mask.
 //   phase 2  for each recorded step only: the lane's state is rebuilt as
-//            P ^ T[step], where P (per lane, VGPRs) is the contribution of
-//            the basis vectors above bit 6 and T (LDS, 128 rows staged per
-//            instance) the contribution of the low 6 bits; the remaining ridge
-//            groups are checked with wave-uniform early exit, then the
-//            facet count |K| (the upper-bound property of Section 4.2) and
-//            x != 0.  Survivors are compacted with a wave ballot and prefix
-//            count into one atomic slot reservation per wave.
+//            P ^ U[v], where P (per lane, VGPRs) is the contribution of the
+//            basis vectors above bit 6 and U (LDS, 64 rows staged per
+//            instance) the contribution of the low 6 bits v of x; the
+//            remaining ridge groups are checked with wave-uniform early exit,
+//            then the facet count |K| (the upper-bound property of Section
+//            4.2) and x != 0.  Survivors are compacted with a wave ballot and
+//            prefix count into per-wave chunks of record slots (one global
+//            atomic per chunk); per-instance counts are flushed once per item.
 // Dot products and parities reduce to AND, XOR and popcount on bit masks, as
 // in Section 2.3.
 #pragma once
@@ -35,6 +36,7 @@
 namespace wpm {
 
 constexpr int DEV_HDR_WORDS = 16;  // must match the host packer's header size
+constexpr int WPM_OUT_CHUNK = 128;  // record slots a wave reserves at a time (>= 64)
 enum {
     D_K = 1, D_KP = 2, D_M = 3, D_W = 4, D_G = 5, D_QS = 6, D_RS = 7, D_MAXF = 8
 };
@@ -47,9 +49,11 @@ struct KArgs {
     uint64_t cap;
     unsigned long long *counts;
     unsigned long long *total;
+    unsigned long long *slots;  // record slots reserved so far (chunk allocator)
     unsigned long long *stats;
     uint64_t *times;
-    int mode;  // 0 direct (one item per workgroup), 1 static stride, 2 dynamic queue
+    const int64_t *bins;  // mode 3: [grid + 1] item ranges per workgroup
+    int mode;  // 0 direct (one item per workgroup), 1 static stride, 2 dynamic queue, 3 packed bins
     int pad;
 };
 
@@ -115,10 +119,12 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
 }
 
 template <int GM, int QS, int WM>
-__global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__ tables,
+__global__ __launch_bounds__(512) void sweep_kernel(const uint32_t *__restrict__ tables,
                                                      const int64_t *__restrict__ offsets,
                                                      const wpm_item *__restrict__ items, KArgs a_in) {
-    extern __shared__ uint32_t lds_T[];  // [128][RS] low-part table, then [kp][RS] rows
+    // LDS: [64][RS] U table (state contribution of every 6-bit low vector),
+    // then [kp][RS] basis rows of the staged instance.
+    extern __shared__ uint32_t lds_U[];
     __shared__ unsigned long long s_item;
     // The launch arguments live in LDS: phase 2 reads them there, which keeps
     // them out of the scalar registers the fast loop needs.
@@ -134,6 +140,9 @@ __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__
     // statistics, kept by lane 0 of each wave in VGPRs (SGPRs are the scarce
     // resource of the fast loop)
     uint32_t n_fire = 0, n_ridge = 0, n_ubt = 0;
+    // per-wave output chunk [out_pos, out_end) of record slots, and the
+    // results found since the last flush
+    uint64_t out_pos = 0, out_end = 0, wave_total = 0;
 
     for (int64_t round = 0;; ++round) {
         int64_t it;
@@ -142,6 +151,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__
             it = a.item_base + (int64_t)blockIdx.x;
         } else if (a.mode == 1) {
             it = (int64_t)blockIdx.x + round * (int64_t)gridDim.x;
+        } else if (a.mode == 3) {
+            const int64_t b0 = a.bins[blockIdx.x], b1 = a.bins[blockIdx.x + 1];
+            it = b0 + round;
+            if (it >= b1) break;
         } else {
             if (tid == 0) s_item = atomicAdd(a.head, 1ull);
             __syncthreads();
@@ -163,30 +176,24 @@ __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__
         const uint32_t maxf = tab[D_MAXF];
         const uint32_t *__restrict__ rows = tab + DEV_HDR_WORDS;
 
-        uint32_t *lds_R = lds_T + WPM_TABLE_ROWS * RS;  // [kp][RS] basis rows
+        uint32_t *lds_R = lds_U + WPM_TABLE_ROWS * RS;  // [kp][RS] basis rows
         if ((int64_t)inst != staged) {
-            // T[idx] = contribution of the low 6 Gray bits at block step
-            // s = idx & 63 with bit 5 toggled by the block parity idx >> 6;
-            // then a copy of the basis rows themselves.
-            const int nT = WPM_TABLE_ROWS * RS;
-            for (int e = tid; e < nT + kp * RS; e += blockDim.x) {
-                uint32_t v = 0;
-                if (e < nT) {
-                    const int idx = e / RS, w = e - idx * RS;
-                    const int s = idx & 63;
-                    const uint32_t xl = (uint32_t)(s ^ (s >> 1)) ^ ((uint32_t)(idx >> 6) << 5);
+            for (int e = tid; e < kp * RS; e += blockDim.x) lds_R[e] = rows[e];
+            __syncthreads();
+            // U[v] = XOR of rows t over the set bits t of v (v < 64)
+            for (int e = tid; e < WPM_TABLE_ROWS * RS; e += blockDim.x) {
+                const int v = e / RS, w = e - v * RS;
+                uint32_t acc = 0;
 #pragma unroll
-                    for (int t = 0; t < 6; ++t)
-                        if ((xl >> t) & 1u) v ^= rows[t * RS + w];
-                } else {
-                    v = rows[e - nT];
-                }
-                lds_T[e] = v;
+                for (int t = 0; t < 6; ++t)
+                    if ((v >> t) & 1) acc ^= lds_R[t * RS + w];
+                lds_U[e] = acc;
             }
             __syncthreads();
             staged = inst;
         }
 
+        uint32_t item_cnt = 0;  // results of this item found by this wave
         // wave-uniform test (readfirstlane tells the compiler so)
         if ((int)__builtin_amdgcn_readfirstlane((uint32_t)(tid & ~63)) < lanes) {
             const bool active = tid < lanes;
@@ -210,9 +217,9 @@ __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__
             const uint64_t nblk = 1ull << (c - 6);
             const int koff = 4 + (G - 1) * mqs;
             for (uint64_t blk = 0; blk < nblk; ++blk) {
-                // ---- phase 1: fast filter over 64 Gray steps
-                // The step mask is set on a rarely taken branch, so a step
-                // costs 8 VALU ops and one conditional branch.
+                // ---- phase 1: fast filter over 64 Gray steps.  The step mask
+                // is set on a rarely taken branch, so a step costs 8 VALU ops
+                // and one conditional branch.
                 uint64_t fire = 0;
 #pragma unroll
                 for (int s = 0; s < 64; ++s) {
@@ -235,8 +242,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__
                     const int s = __builtin_ctzll(fire);
                     fire &= fire - 1;
                     if (lane == 0) ++n_fire;
-                    const int idx = ((int)(blk & 1ull) << 6) | s;
-                    const uint32_t *T = lds_T + idx * RS;
+                    // low 6 bits of x at this step: Gray code of s, bit 5
+                    // toggled by the block parity
+                    const int v = (s ^ (s >> 1)) ^ ((int)(blk & 1ull) << 5);
+                    const uint32_t *T = lds_U + v * RS;
                     bool pass = active && fail4(P[0] ^ T[0], P[1] ^ T[1], P[2] ^ T[2], P[3] ^ T[3]) == 0u;
                     // groups in decreasing rejection order; stop once no lane passes
                     int Gp = G, Qp = mqs;
@@ -274,21 +283,31 @@ __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__
                         }
                         if (bal) {
                             const uint32_t nb = (uint32_t)__builtin_popcountll(bal);
-                            unsigned long long base = 0;
-                            if (lane == 0) {
-                                base = atomicAdd(a.total, (unsigned long long)nb);
-                                atomicAdd(a.counts + inst, (unsigned long long)nb);
+                            item_cnt += nb;
+                            if (out_pos + nb > out_end) {
+                                // close the current chunk with sentinel
+                                // records and reserve a new one (one global
+                                // atomic per WPM_OUT_CHUNK record slots)
+                                for (uint64_t e0 = out_pos + (uint64_t)lane; e0 < out_end && e0 < a.cap;
+                                     e0 += 64) {
+                                    a.surv[2 * e0] = 0;
+                                    a.surv[2 * e0 + 1] = ~0ull;
+                                }
+                                unsigned long long base = 0;
+                                if (lane == 0) base = atomicAdd(a.slots, (unsigned long long)WPM_OUT_CHUNK);
+                                out_pos = rfl64(base);
+                                out_end = out_pos + WPM_OUT_CHUNK;
                             }
-                            base = rfl64(base);
                             if (ok) {
                                 const uint32_t rk = __builtin_amdgcn_mbcnt_hi(
                                     (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                                const uint64_t pos = base + rk;
+                                const uint64_t pos = out_pos + rk;
                                 if (pos < a.cap) {
                                     a.surv[2 * pos] = x;
                                     a.surv[2 * pos + 1] = inst;
                                 }
                             }
+                            out_pos += nb;
                         }
                     }
                 }
@@ -308,12 +327,20 @@ __global__ __launch_bounds__(256) void sweep_kernel(const uint32_t *__restrict__
                 }
             }
         }
+        if (item_cnt && lane == 0) atomicAdd(a.counts + inst, (unsigned long long)item_cnt);
+        wave_total += item_cnt;
         __syncthreads();
         if (tid == 0 && a.times) {
             a.times[2 * it] = t_start;
             a.times[2 * it + 1] = __builtin_amdgcn_s_memrealtime();
         }
     }
+    // close this wave's output chunk and publish its totals
+    for (uint64_t e0 = out_pos + (uint64_t)lane; e0 < out_end && e0 < a.cap; e0 += 64) {
+        a.surv[2 * e0] = 0;
+        a.surv[2 * e0 + 1] = ~0ull;
+    }
+    if (lane == 0 && wave_total) atomicAdd(a.total, (unsigned long long)wave_total);
     if (a.stats && lane == 0 && (n_fire | n_ridge | n_ubt)) {
         atomicAdd(a.stats + 0, (unsigned long long)n_fire);
         atomicAdd(a.stats + 1, (unsigned long long)n_ridge);

@@ -150,6 +150,20 @@ def device_query():
     return cus.value, clk.value, lds.value
 
 
+def _gm(groups: int) -> int:
+    return 2 if groups <= 2 else 4 if groups <= 4 else 8 if groups <= 8 else 16
+
+
+def _wm(words: int) -> int:
+    return 4 if words <= 4 else 16 if words <= 16 else 32
+
+
+def template_class(info) -> int:
+    """Code of the kernel instantiation an instance needs: (groups, slot
+    stride, facet words) rounded up to the instantiated sizes."""
+    return _gm(info.groups) * 10000 + info.slots * 100 + _wm(info.W)
+
+
 class DeviceBatch:
     """Packed tables of a list of prepared instances, resident in HBM."""
 
@@ -168,15 +182,21 @@ class DeviceBatch:
         self.tables = torch.from_numpy(host.view(np.int32)).to(device)
         self.offsets = torch.from_numpy(offs).to(device)
         self.k = np.array([p.k for p in self.preps], dtype=np.int32)
-        self.c_batch = L.Batch(
-            num_instances=len(self.preps),
-            max_row_words=max([p.info.row_words for p in self.preps] + [4]),
-            max_groups=max([p.info.groups for p in self.preps] + [1]),
-            max_slots=max([p.info.slots for p in self.preps] + [4]),
-            max_words=max([p.info.W for p in self.preps] + [1]),
-            max_kp=max([max(p.k, 7) for p in self.preps] + [7]),
-            d_tables=self.tables.data_ptr(), d_offsets=self.offsets.data_ptr())
+        self.cls = np.array([template_class(p.info) for p in self.preps], dtype=np.int64)
+        self.c_batch = self._batch_of(self.preps)
+        self.class_batches = {int(c): self._batch_of([p for p, q in zip(self.preps, self.cls) if q == c])
+                              for c in np.unique(self.cls)}
         self.table_bytes = total * 4
+
+    def _batch_of(self, members) -> "L.Batch":
+        return L.Batch(
+            num_instances=len(self.preps),
+            max_row_words=max([p.info.row_words for p in members] + [4]),
+            max_groups=max([p.info.groups for p in members] + [1]),
+            max_slots=max([p.info.slots for p in members] + [4]),
+            max_words=max([p.info.W for p in members] + [1]),
+            max_kp=max([max(p.k, 7) for p in members] + [7]),
+            d_tables=self.tables.data_ptr(), d_offsets=self.offsets.data_ptr())
 
     @property
     def vectors(self) -> int:
@@ -198,16 +218,69 @@ def build_queue(k: np.ndarray, cbits: int, lanes: int, cost: Optional[np.ndarray
     st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, len(ka), cbits, lanes, min_items_per_instance,
                              max_items_per_instance, order, items, n.value, ctypes.byref(n))
     L.check("wpm_build_queue", st)
-    arr = np.frombuffer(items, dtype=np.dtype([("instance", "<u4"), ("cbits", "<u2"),
-                                               ("lanes", "<u2"), ("first", "<u8")]),
-                        count=n.value).copy()
+    arr = np.frombuffer(items, dtype=ITEM_DTYPE, count=n.value).copy()
     return arr
+
+
+ITEM_DTYPE = np.dtype([("instance", "<u4"), ("cbits", "<u2"), ("lanes", "<u2"), ("first", "<u8")])
+
+
+def pack_bins(items: np.ndarray, bins: int, cost: Optional[np.ndarray] = None):
+    """LPT assignment of items to `bins` workgroups -> (items bin by bin, offsets[bins+1], max load)."""
+    items = np.ascontiguousarray(items)
+    n = len(items)
+    src = (L.Item * max(1, n)).from_buffer_copy(items.tobytes() if n else bytes(16))
+    out = (L.Item * max(1, n))()
+    offs = np.zeros(bins + 1, dtype=np.int64)
+    mx = ctypes.c_double(0)
+    ca = None if cost is None else np.ascontiguousarray(cost, dtype=np.float32)
+    st = L.lib().wpm_pack_bins(src, n, None if ca is None else _ptr(ca, L.c_f32p), bins, out,
+                               _ptr(offs, L.c_i64p), ctypes.byref(mx))
+    L.check("wpm_pack_bins", st)
+    arr = np.frombuffer(out, dtype=ITEM_DTYPE, count=n).copy()
+    return arr, offs, mx.value
+
+
+def persistent_grid(batch: "DeviceBatch", wg_size: int, cls: Optional[int] = None) -> int:
+    """Workgroups of a persistent launch (of one template class, or of the
+    whole batch under its largest template)."""
+    cb = batch.c_batch if cls is None else batch.class_batches[int(cls)]
+    g = ctypes.c_int32(0)
+    L.check("wpm_persistent_grid", L.lib().wpm_persistent_grid(ctypes.byref(cb), wg_size,
+                                                               ctypes.byref(g)))
+    return g.value
+
+
+@dataclass
+class Segment:
+    """Items [start, end) launched together under one kernel template."""
+    cls: Optional[int]
+    start: int
+    end: int
+    bins: Optional[np.ndarray] = None
+
+
+def split_by_class(batch: "DeviceBatch", items: np.ndarray):
+    """Stable grouping of items by their instance's template class, largest
+    class first -> (items, segments)."""
+    if len(items) == 0:
+        return items, []
+    c = batch.cls[items["instance"].astype(np.int64)]
+    codes = sorted(np.unique(c), reverse=True)
+    out, segs, pos = [], [], 0
+    for code in codes:
+        sel = items[c == code]
+        out.append(sel)
+        segs.append(Segment(int(code), pos, pos + len(sel)))
+        pos += len(sel)
+    return np.concatenate(out), segs
 
 
 @dataclass
 class SweepResult:
     counts: np.ndarray
     total: int
+    slots: int
     stats: np.ndarray
     ms: float = 0.0
     item_times: Optional[np.ndarray] = None
@@ -224,16 +297,32 @@ class Sweeper:
         self.cap = cap
         self.surv = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=device)
         self.counts = torch.empty(max(1, len(batch.preps)), dtype=torch.int64, device=device)
-        self.total = torch.empty(1, dtype=torch.int64, device=device)
+        self.total = torch.empty(2, dtype=torch.int64, device=device)  # [results, record slots]
         self.stats = torch.empty(8, dtype=torch.int64, device=device)
         self.scratch = torch.empty(4, dtype=torch.int64, device=device)
         self._items_dev = None
         self._items_host = None
         self._times = None
+        self._segments = []
+        self._seg_bins = []
 
-    def set_items(self, items: np.ndarray, want_times: bool = False):
+    def set_items(self, items: np.ndarray, want_times: bool = False,
+                  bin_offsets: Optional[np.ndarray] = None, segments=None,
+                  split_classes: bool = True):
+        """Upload the items.  By default items are grouped by kernel template
+        class and launched class by class; `segments` gives that grouping
+        explicitly (packed plans carry per-segment bins); bin_offsets alone
+        means one packed launch under the batch-wide template."""
         torch = self.torch
+        if segments is None:
+            if bin_offsets is not None or not split_classes:
+                segments = [Segment(None, 0, len(items), bin_offsets)]
+            else:
+                items, segments = split_by_class(self.batch, np.ascontiguousarray(items))
         self._items_host = np.ascontiguousarray(items)
+        self._segments = segments
+        self._seg_bins = [None if sg.bins is None else torch.from_numpy(
+            np.ascontiguousarray(sg.bins, np.int64)).to(self.surv.device) for sg in segments]
         raw = self._items_host.view(np.int64).reshape(-1) if len(items) else np.zeros(2, np.int64)
         self._items_dev = torch.from_numpy(raw.copy()).to(self.surv.device)
         self._times = (torch.zeros((max(1, len(items)), 2), dtype=torch.int64, device=self.surv.device)
@@ -244,21 +333,33 @@ class Sweeper:
         if stream is None:
             stream = torch.cuda.current_stream()
         items = self._items_host
-        s = L.Sched(mode=mode, wg_size=wg_size, grid=grid, reserved=0,
-                    d_items=self._items_dev.data_ptr(),
-                    h_items=items.ctypes.data if len(items) else None,
-                    num_items=len(items), d_scratch=self.scratch.data_ptr(),
-                    d_item_times=self._times.data_ptr() if self._times is not None else None)
-        st = L.lib().wpm_enumerate(ctypes.byref(self.batch.c_batch), ctypes.byref(s),
-                                   self.surv.data_ptr(), self.cap, self.counts.data_ptr(),
-                                   self.total.data_ptr(), self.stats.data_ptr(),
-                                   ctypes.c_void_p(stream.cuda_stream))
-        L.check("wpm_enumerate", st)
+        segs = self._segments or [Segment(None, 0, 0)]
+        for i, sg in enumerate(segs):
+            cb = self.batch.c_batch if sg.cls is None else self.batch.class_batches[sg.cls]
+            n = sg.end - sg.start
+            bins = self._seg_bins[i] if self._segments else None
+            s = L.Sched(mode=mode, wg_size=wg_size, grid=grid, flags=L.FLAG_ACCUMULATE if i else 0,
+                        d_items=self._items_dev.data_ptr() + 16 * sg.start,
+                        h_items=items.ctypes.data + 16 * sg.start if n else None,
+                        num_items=n, d_scratch=self.scratch.data_ptr(),
+                        d_item_times=(self._times.data_ptr() + 16 * sg.start) if self._times is not None else None,
+                        d_bin_offsets=bins.data_ptr() if bins is not None else None)
+            if mode == L.SCHED_PACKED:
+                if bins is None:
+                    raise ValueError("packed mode needs per-segment bins")
+                s.grid = len(bins) - 1
+            st = L.lib().wpm_enumerate(ctypes.byref(cb), ctypes.byref(s), self.surv.data_ptr(),
+                                       self.cap, self.counts.data_ptr(), self.total.data_ptr(),
+                                       self.stats.data_ptr(), ctypes.c_void_p(stream.cuda_stream))
+            L.check("wpm_enumerate", st)
 
-    def fetch_records(self, n: int):
-        """Copy the first n survivor records {x, instance} into a pinned host
-        buffer (allocated once) and return a numpy view of them."""
+    def fetch_records(self, n: Optional[int] = None):
+        """Copy the first n record slots (default: all used slots) into a
+        pinned host buffer (allocated once) and return a numpy view of them.
+        Unused slots carry the instance ~0 and are kept in the view."""
         torch = self.torch
+        if n is None:
+            n = int(self.total[1].item())
         n = min(int(n), self.cap)
         if getattr(self, "_pinned", None) is None or self._pinned.shape[0] < n:
             self._pinned = torch.empty((max(n, 1), 2), dtype=torch.int64, pin_memory=True)
@@ -270,7 +371,8 @@ class Sweeper:
     def result(self) -> SweepResult:
         self.torch.cuda.synchronize()
         counts = self.counts[:len(self.batch.preps)].cpu().numpy().astype(np.uint64)
-        return SweepResult(counts=counts, total=int(self.total.item()),
+        tot = self.total.cpu().numpy()
+        return SweepResult(counts=counts, total=int(tot[0]), slots=int(tot[1]),
                            stats=self.stats.cpu().numpy(),
                            item_times=None if self._times is None else self._times.cpu().numpy(),
                            items=self._items_host)

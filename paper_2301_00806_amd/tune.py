@@ -1,0 +1,102 @@
+"""Autotuner for the persistent sweep: lane chunk bits and workgroup size.
+
+It times candidate launch shapes on a sample of the batch (the instances that
+hold most of the work, plus a spread of small ones), keeps the fastest, and
+caches the choice in a JSON file keyed by the GPU architecture and a shape
+bucket of the batch (kernel template class and log2 of the vectors per
+instance).  Counts are identical for every shape; the tuner checks that too.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+from . import engine as E
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "wpm_tune.json")
+CBITS = (12, 14, 16, 18)
+WGS = (128, 256)
+
+
+def shape_key(batch: "E.DeviceBatch") -> str:
+    import torch
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    b = batch.c_batch
+    gm = 2 if b.max_groups <= 2 else 4 if b.max_groups <= 4 else 8 if b.max_groups <= 8 else 16
+    wm = 4 if b.max_words <= 4 else 16 if b.max_words <= 16 else 32
+    lv = int(np.log2(max(1.0, batch.vectors / max(1, len(batch.preps)))))
+    return f"{arch}/gm{gm}/qs{b.max_slots}/wm{wm}/v{lv}"
+
+
+def _sample(preps, budget_vectors: float):
+    order = sorted(range(len(preps)), key=lambda i: -preps[i].k)
+    chosen, tot = [], 0.0
+    for i in order:
+        v = float(1 << preps[i].k)
+        if tot + v > budget_vectors and chosen:
+            continue
+        chosen.append(i)
+        tot += v
+        if tot >= budget_vectors:
+            break
+    small = [i for i in order[::max(1, len(order) // 64)] if i not in chosen]
+    return sorted(set(chosen + small))
+
+
+def tune(preps: Sequence, cache: Optional[str] = DEFAULT_CACHE, budget_vectors: float = 2e11,
+         cbits=CBITS, wgs=WGS, repeats: int = 2, force: bool = False, log=None) -> Dict:
+    import torch
+    full = E.DeviceBatch(preps)
+    key = shape_key(full)
+    db = {}
+    if cache and os.path.exists(cache):
+        try:
+            with open(cache) as f:
+                db = json.load(f)
+        except (OSError, ValueError):
+            db = {}
+    if key in db and not force:
+        return dict(db[key], cached=True, key=key)
+    idx = _sample(preps, budget_vectors)
+    sub = [preps[i] for i in idx]
+    batch = E.DeviceBatch(sub)
+    sw = E.Sweeper(batch, cap=1 << 24)
+    vec = batch.vectors
+    results, ref = [], None
+    for wg in wgs:
+        for cb in cbits:
+            items = E.build_queue(batch.k, cb, wg, cost=np.ones(len(sub), np.float32), order=1)
+            sw.set_items(items)
+            sw.launch(L.SCHED_DYNAMIC, wg_size=wg)
+            r = sw.result()
+            if ref is None:
+                ref = r.counts.copy()
+            if not np.array_equal(r.counts, ref):
+                raise RuntimeError(f"counts changed with cbits={cb} wg={wg}")
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(repeats):
+                sw.launch(L.SCHED_DYNAMIC, wg_size=wg)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / repeats
+            results.append({"cbits": cb, "wg": wg, "ms": ms, "vectors_per_s": vec / ms * 1e3})
+            if log:
+                log(f"tune cbits={cb} wg={wg}: {ms:.2f} ms ({vec / ms * 1e3:.3e} vectors/s)")
+    best = max(results, key=lambda r: r["vectors_per_s"])
+    entry = {"cbits": best["cbits"], "wg": best["wg"], "sample_instances": len(sub),
+             "sample_vectors": vec, "results": results, "when": time.time()}
+    if cache:
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        db[key] = entry
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1)
+        os.replace(tmp, cache)
+    return dict(entry, cached=False, key=key)

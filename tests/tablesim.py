@@ -66,11 +66,10 @@ def survivors_walk(tab, cbits=7):
     R = rows(tab)
     kp, k = h["kp"], h["k"]
     c = min(max(cbits, 7), kp)
-    T = np.zeros((128, R.shape[1]), dtype=np.uint64)
-    for idx in range(128):
-        s = idx & 63
-        xl = (s ^ (s >> 1)) ^ ((idx >> 6) << 5)
-        T[idx] = state(R[:6], xl)
+    # U[v]: state contribution of the 6-bit low vector v (64 rows staged in LDS)
+    U = np.zeros((64, R.shape[1]), dtype=np.uint64)
+    for v in range(64):
+        U[v] = state(R[:6], v)
     out = []
     for j in range(1 << (kp - c)):
         i0 = j << c
@@ -87,8 +86,8 @@ def survivors_walk(tab, cbits=7):
                     t = (s + 1 & -(s + 1)).bit_length() - 1
                     s4 ^= R[t, :4]
             for s in fire:
-                idx = ((blk & 1) << 6) | s
-                v = P ^ T[idx]
+                low = (s ^ (s >> 1)) ^ ((blk & 1) << 5)
+                v = P ^ U[low]
                 i = i0 + (blk << 6) + s
                 x = i ^ (i >> 1)
                 assert np.array_equal(v, state(R, x))

@@ -109,6 +109,11 @@ def test_pack_rejects_large_k_and_bad_input():
     assert lib.wpm_build_candidates(2, 3, E._ptr(lam), E._ptr(out), 8, ctypes.byref(Mo)) == L.WPM_EINVAL
 
 
+def test_build_queue_skips_k0():
+    items = E.build_queue(np.array([0, 8, 0], dtype=np.int32), 7, 64)
+    assert set(items["instance"].tolist()) == {1}
+
+
 def test_build_queue_covers_every_chunk_once():
     k = np.array([7, 12, 20, 9], dtype=np.int32)
     for cb, lanes, mx, order in [(7, 64, 0, 0), (10, 256, 0, 1), (7, 128, 4, 1)]:
@@ -127,3 +132,42 @@ def test_build_queue_covers_every_chunk_once():
         if order == 1:
             cost = [float([1, 2, 3, 4][it["instance"]]) * (int(it["lanes"]) << int(it["cbits"])) for it in items]
             assert cost == sorted(cost, reverse=True)
+
+
+def test_pack_bins_assigns_every_item_once_lpt():
+    k = np.array([7, 12, 16, 9, 20], dtype=np.int32)
+    items = E.build_queue(k, 9, 64, min_items_per_instance=2)
+    cost = np.array([1.0, 0.5, 2.0, 1.0, 0.25], np.float32)
+    out, offs, mx = E.pack_bins(items, 7, cost)
+    assert offs[0] == 0 and offs[-1] == len(items)
+    key = lambda a: sorted((int(i["instance"]), int(i["first"]), int(i["cbits"])) for i in a)
+    assert key(out) == key(items)
+    c = lambda it: float(cost[it["instance"]]) * int(it["lanes"]) * (1 << int(it["cbits"]))
+    loads = [sum(c(out[j]) for j in range(offs[b], offs[b + 1])) for b in range(7)]
+    assert abs(max(loads) - mx) < 1e-6 * mx
+    # LPT bound: makespan <= 4/3 * OPT, and OPT >= max(mean load, largest item)
+    lower = max(sum(loads) / 7, max(c(it) for it in items))
+    assert max(loads) <= 4.0 / 3.0 * lower + 1e-9 * lower
+
+
+def test_single_hip_runtime_in_process():
+    # libwpm.so must bind to the HIP runtime torch already loaded (one runtime
+    # per process: shared streams and device memory)
+    import os
+    L.lib()
+    maps = open(f"/proc/{os.getpid()}/maps").read()
+    hips = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
+    assert len(hips) == 1, hips
+
+
+def test_template_class_split_keeps_every_item():
+    k = np.array([7, 12, 16, 9, 20], dtype=np.int32)
+    items = E.build_queue(k, 9, 64)
+
+    class FakeBatch:
+        cls = np.array([40416, 20416, 40416, 80416, 20416])
+    out, segs = E.split_by_class(FakeBatch, items)
+    assert len(out) == len(items) and segs[0].start == 0 and segs[-1].end == len(items)
+    assert [s.cls for s in segs] == [80416, 40416, 20416]
+    for s in segs:
+        assert set(FakeBatch.cls[out[s.start:s.end]["instance"]]) == {s.cls}
