@@ -29,7 +29,10 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-INT32_PEAK = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: int32 VALU lane-ops/s
+# Integer VALU peak: 256 CUs x 128 32-bit lane-ops per clock (a wave64 VALU op
+# every 2 clocks on each of 4 SIMDs, the same issue rate as fp32 FMA behind the
+# 157.3 TFLOP/s figure) x 2.4 GHz.  wpm_valu_probe measures it on the device.
+INT32_PEAK = 256 * 128 * 2.4e9
 ALG_OPS_PER_VECTOR = 8             # fast filter: 4 XOR + 3 threshold ops + 1 compare
 
 
@@ -104,6 +107,8 @@ def main():
     ap.add_argument("--train-instances", type=int, default=4096)
     ap.add_argument("--epochs", type=int, default=200)
     ap.add_argument("--learned-policy", default="dynamic", choices=["packed", "dynamic"])
+    ap.add_argument("--only-learned", action="store_true",
+                    help="time only the learned schedule (profiling runs)")
     ap.add_argument("--no-split", action="store_true",
                     help="one launch under the largest kernel template instead of one per class")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -148,7 +153,8 @@ def main():
     Xtr, Ttr, _ = S.measure_labels(train_preps, cbits=12, wg=args.wg)
     model = CM.CostModel(seed=0)
     model.fit(Xtr, Ttr, epochs=args.epochs, lr=3e-3, batch=512)
-    train_loss = model.loss(Xtr, Ttr)
+    okt = np.isfinite(Ttr).all(1)
+    train_loss = model.loss(Xtr[okt], Ttr[okt])
     log(f"cost model trained on {len(Xtr)} instances in {time.time() - t:.1f}s, loss {train_loss:.4f}")
 
     feats = CM.features_of(preps)
@@ -166,13 +172,13 @@ def main():
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        kern_ms = []
+        kern_ms, seg_ms = [], {}
         t0 = time.perf_counter()
         for _ in range(steps):
             plan = make()                              # scheduling is part of the step
             sw.set_items(plan.items, segments=plan.segments)
             e0.record(stream)
-            sw.launch(plan.mode, wg_size=args.wg, stream=stream)
+            sw.launch(plan.mode, wg_size=args.wg, stream=stream, seg_events=True)
             e1.record(stream)
             counts = sw.counts[:len(preps)].cpu()      # synchronises the stream
             tot, slots = (int(v) for v in sw.total.cpu())
@@ -180,14 +186,28 @@ def main():
                 raise SystemExit(f"survivor buffer too small: {slots} > {sw.cap}")
             rec = sw.fetch_records(slots)              # survivor records to pinned host memory
             kern_ms.append(e0.elapsed_time(e1))
+            for cls, a0, a1 in sw.seg_events:
+                seg_ms.setdefault(cls, []).append(a0.elapsed_time(a1))
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
         res = sw.result()
         log(f"{label}: kernel {np.mean(kern_ms):.2f} ms, step {wall * 1e3:.2f} ms, "
             f"{vectors / wall:.3e} vectors/s, total WPMs {res.total}, stats {res.stats[:3]}")
+        timed_plan.seg_ms = {c: float(np.mean(v)) for c, v in seg_ms.items()}
         return wall, float(np.mean(kern_ms)), res
 
     t_b, k_b, res_b = timed_plan(plan_learned, args.steps, args.warmup, f"learned-{args.learned_policy}")
+    seg_ms = dict(timed_plan.seg_ms)
+    # the dominant launch: the template class holding most of the vectors
+    cls_vec = {}
+    for p, c in zip(preps, batch.cls):
+        if p.k > 0:
+            cls_vec[int(c)] = cls_vec.get(int(c), 0) + (1 << p.k)
+    dom = max(cls_vec, key=cls_vec.get)
+    dom_ms = seg_ms[dom]
+    dom_name = "sweep_kernel<%d, %d, %d>" % (dom // 10000, (dom // 100) % 100, dom % 100)
+    log(f"dominant launch {dom_name}: {cls_vec[dom]:.4e} vectors in {dom_ms:.2f} ms "
+        f"({cls_vec[dom] / dom_ms * 1e3:.3e} vectors/s); per-class ms {seg_ms}")
     out = {}
     sp = not args.no_split
     others = [("static", lambda: S.make_plan(batch, "static", cbits=args.cbits, wg=args.wg, split=sp)),
@@ -199,7 +219,7 @@ def main():
     other_pol = "packed" if args.learned_policy == "dynamic" else "dynamic"
     others.append((f"{other_pol}_model", lambda: S.make_plan(
         batch, other_pol, cost=S.per_vector_cost(model, feats), cbits=args.cbits, wg=args.wg, split=sp)))
-    for name, mk in others:
+    for name, mk in ([] if args.only_learned else others):
         if args.no_static and name == "static":
             continue
         st = max(1, args.steps // 2) if name != "plain" else 1
@@ -208,11 +228,12 @@ def main():
         out[name] = {"value": vectors / t_o, "ms_per_step": t_o * 1e3, "kernel_ms": k_o}
 
     # model error on the fresh instances: measured per-instance time vs prediction
-    _, Tte, _ = S.measure_labels(preps, cbits=args.cbits, wg=args.wg, repeats=1)
+    _, Tte, _ = S.measure_labels(preps, cbits=args.cbits, wg=args.wg, repeats=1) if not args.only_learned \
+        else (None, model.predict(feats), None)
     pred = model.predict(feats)
     ok = np.isfinite(Tte[:, 0])
     err = pred[ok, 0] - Tte[ok, 0]
-    base = np.median(Ttr[:, 0]) - Tte[ok, 0]       # "cost proportional to 2^k": constant ns/vector
+    base = np.median(Ttr[okt, 0]) - Tte[ok, 0]     # "cost proportional to 2^k": constant ns/vector
     model_err = {"log_rmse": float(np.sqrt(np.mean(err ** 2))),
                  "mape": float(np.mean(np.abs(np.expm1(err)))),
                  "log_rmse_pow2_heuristic": float(np.sqrt(np.mean(base ** 2))),
@@ -227,7 +248,17 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
-    achieved = ALG_OPS_PER_VECTOR * vectors / (k_b * 1e-3) / 1e12
+    achieved = ALG_OPS_PER_VECTOR * cls_vec[dom] / (dom_ms * 1e-3) / 1e12
+    probe = E.valu_probe(0, 4)
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+    if os.path.exists(tpath):
+        import hashlib
+        src = open(os.path.join(ROOT, "paper_2301_00806_amd", "csrc", "sweep_kernel.h"), "rb").read()
+        with open(tpath) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_sha256") == hashlib.sha256(src).hexdigest() and tr.get("kernel") == dom_name:
+            traffic = tr.get("bytes_per_launch")
     line = {
         "metric": "kernel vectors checked/sec + WPM count (bit-exact); batched+learned vs plain",
         "value": vectors / t_b,
@@ -255,8 +286,9 @@ def main():
                                                 "wg": tuned["wg"], "cached": tuned["cached"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": INT32_PEAK / 1e12,
                      "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved / (INT32_PEAK / 1e12),
-                     "traffic": None,
-                     "ops_per_vector": ALG_OPS_PER_VECTOR},
+                     "traffic": traffic, "kernel": dom_name, "kernel_ms": dom_ms,
+                     "vectors_per_launch": cls_vec[dom], "ops_per_vector": ALG_OPS_PER_VECTOR,
+                     "measured_int32_xor_peak": probe / 1e12},
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(preps, args.cpu_budget)

@@ -165,6 +165,9 @@ enum {
  *   k[num]           kernel dimension of each instance
  *   cost[num]        relative cost per vector (NULL = 1.0 for all); an item's
  *                    cost is cost[i] * vectors in the item
+ *   group[num]       optional launch group of each instance (NULL = all 0):
+ *                    items come out group by group, in decreasing group key,
+ *                    so each group can be launched under its own kernel template
  *   cbits            lane chunk bits (clamped to [7, max(k,7)] per instance)
  *   lanes            lanes per item (workgroup size)
  *   min_items_per_instance  lower cbits (down to 7) until an instance has at
@@ -172,13 +175,17 @@ enum {
  *                    small instance still occupies whole workgroups
  *   max_items_per_instance  > 0: coarsen chunks so an instance yields at most
  *                    this many items (raises cbits; applied after the minimum)
- *   order            0 = instance order, 1 = descending item cost (LPT)
- *   Instances with k = 0 yield no items (their only vector is x = 0).
+ *   order            0 = instance order, 1 = decreasing item cost inside a
+ *                    group (instance by instance: longest-processing-time
+ *                    first up to each instance's partial last item)
  *   items, cap       output (host); *n_out = item count (WPM_ECAP if > cap)
+ *   items_per_instance  optional [num] output: items of each instance
+ *   Instances with k = 0 yield no items (their only vector is x = 0).
  */
-int wpm_build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits,
-                    int32_t lanes, int32_t min_items_per_instance, int32_t max_items_per_instance,
-                    int32_t order, wpm_item *items, int64_t cap, int64_t *n_out);
+int wpm_build_queue(const int32_t *k, const float *cost, const int32_t *group, int32_t num,
+                    int32_t cbits, int32_t lanes, int32_t min_items_per_instance,
+                    int32_t max_items_per_instance, int32_t order, wpm_item *items, int64_t cap,
+                    int64_t *n_out, int64_t *items_per_instance);
 
 /*
  * Pack items into `bins` workgroup bins by longest-processing-time-first:
@@ -249,6 +256,13 @@ int wpm_enumerate(const wpm_batch *batch, const wpm_sched *sched, uint64_t *d_su
 /* Device facts the scheduler needs: compute units, the s_memrealtime clock
  * rate (kHz, the unit of d_item_times) and the LDS limit per workgroup. */
 int wpm_device_query(int32_t *num_cus, int64_t *wallclock_khz, int32_t *lds_per_block);
+
+/* Integer VALU throughput probe (diagnostic; allocates and synchronises the
+ * device, so never call it under graph capture).  op: 0 = 32-bit XOR with
+ * register operands, 1 = 3-input bit logic (v_bitop3), 2 = AND-OR; one
+ * 256-thread workgroup per CU per unit of waves_per_simd (1..8).
+ * *lane_ops_per_s receives the measured 32-bit lane operations per second. */
+int wpm_valu_probe(int op, int waves_per_simd, int iters, double *lane_ops_per_s);
 
 /* Host view of an instance for wpm_collect. */
 typedef struct wpm_host_instance {

@@ -99,9 +99,9 @@ def lib():
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, c_u32p,
                                     ctypes.c_int64, ctypes.POINTER(InstanceInfo)]
     L.wpm_build_queue.restype = ctypes.c_int
-    L.wpm_build_queue.argtypes = [c_i32p, c_f32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Item),
-                                  ctypes.c_int64, c_i64p]
+    L.wpm_build_queue.argtypes = [c_i32p, c_f32p, c_i32p, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.POINTER(Item), ctypes.c_int64, c_i64p, c_i64p]
     L.wpm_pack_bins.restype = ctypes.c_int
     L.wpm_pack_bins.argtypes = [ctypes.POINTER(Item), ctypes.c_int64, c_f32p, ctypes.c_int32,
                                 ctypes.POINTER(Item), c_i64p, ctypes.POINTER(ctypes.c_double)]
@@ -111,6 +111,8 @@ def lib():
                                 ctypes.c_void_p, ctypes.c_void_p]
     L.wpm_persistent_grid.restype = ctypes.c_int
     L.wpm_persistent_grid.argtypes = [ctypes.POINTER(Batch), ctypes.c_int32, c_i32p]
+    L.wpm_valu_probe.restype = ctypes.c_int
+    L.wpm_valu_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     L.wpm_device_query.restype = ctypes.c_int
     L.wpm_device_query.argtypes = [c_i32p, c_i64p, c_i32p]
     L.wpm_collect.restype = ctypes.c_int
@@ -140,6 +142,6 @@ def check(call: str, status: int, ok=(WPM_OK,)) -> int:
 # Every symbol include/wpm.h declares.
 EXPORTED = ("wpm_strerror", "wpm_last_hip_error", "wpm_build_candidates", "wpm_kernel_basis",
             "wpm_ubt_bound", "wpm_pack_instance", "wpm_build_queue", "wpm_pack_bins", "wpm_enumerate",
-            "wpm_device_query", "wpm_persistent_grid", "wpm_collect", "wpm_mlp_work_floats", "wpm_mlp_forward",
+            "wpm_device_query", "wpm_persistent_grid", "wpm_valu_probe", "wpm_collect", "wpm_mlp_work_floats", "wpm_mlp_forward",
             "wpm_mlp_grad", "wpm_mlp_adam")
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS, MLP_NORM = 16, 64, 2, 5378, 36

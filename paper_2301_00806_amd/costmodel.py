@@ -98,8 +98,9 @@ class CostModel:
             batch: int = 1024, weight_decay: float = 1e-4, seed: int = 0, log_every: int = 0):
         """Mini-batch Adam on the GPU; sets the normalisation from the data."""
         torch = self.torch
-        X = np.ascontiguousarray(X, np.float32)
-        T = np.ascontiguousarray(T, np.float32)
+        ok = np.isfinite(T).all(1)
+        X = np.ascontiguousarray(X[ok], np.float32)
+        T = np.ascontiguousarray(T[ok], np.float32)
         self.norm = torch.from_numpy(make_norm(X, T)).to(self.device)
         Xd = torch.from_numpy(X).to(self.device)
         Td = torch.from_numpy(T).to(self.device)
@@ -158,11 +159,17 @@ class CostModel:
 def labels_from_sweep(preps: Sequence, res, clock_khz: float) -> np.ndarray:
     """[ln(ns per vector), log10(density)] per instance from a timed sweep:
     the sum over an instance's items of (end - start) stamps, converted with
-    the stamp clock rate, divided by its 2^k vectors."""
+    the stamp clock rate, divided by its 2^k vectors.  Instances that were not
+    swept (k = 0: no items) get NaN labels."""
     items, times = res.items, res.item_times
     ns = np.zeros(len(preps))
-    dur = (times[:, 1] - times[:, 0]).astype(np.float64) * (1e6 / clock_khz)
-    np.add.at(ns, items["instance"].astype(np.int64), dur)
+    swept = np.zeros(len(preps), dtype=bool)
+    dur = (times[:len(items), 1] - times[:len(items), 0]).astype(np.float64) * (1e6 / clock_khz)
+    inst = items["instance"].astype(np.int64)
+    np.add.at(ns, inst, dur)
+    swept[inst] = True
     vec = np.array([float(1 << p.k) for p in preps])
     dens = res.counts.astype(np.float64) / vec
-    return np.stack([np.log(np.maximum(ns / vec, 1e-6)), np.log10(np.maximum(dens, 1e-9))], 1).astype(np.float32)
+    lab = np.stack([np.log(np.maximum(ns / vec, 1e-6)), np.log10(np.maximum(dens, 1e-9))], 1)
+    lab[~swept] = np.nan      # not swept (k = 0): no measurement
+    return lab.astype(np.float32)

@@ -11,6 +11,7 @@ int device_query(int32_t *num_cus, int64_t *wallclock_khz, int32_t *lds_per_bloc
 int persistent_grid(const wpm_batch *b, int wg_size, int32_t *grid);
 const char *last_hip_error();
 int64_t mlp_work_floats(int B);
+int valu_probe_run(int op, int waves_per_simd, int iters, double *lane_ops_per_s);
 int mlp_forward_launch(const float *params, const float *norm, const float *X, int B, float *Y,
                        void *stream);
 int mlp_grad_launch(const float *params, const float *norm, const float *X, const float *T, int B,
@@ -54,11 +55,12 @@ int wpm_pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uin
     return wpm::pack_instance(n, m, facets, M, basis, k, max_facets, seed, table, cap_words, info);
 }
 
-int wpm_build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits,
-                    int32_t lanes, int32_t min_items_per_instance, int32_t max_items_per_instance,
-                    int32_t order, wpm_item *items, int64_t cap, int64_t *n_out) {
-    return wpm::build_queue(k, cost, num, cbits, lanes, min_items_per_instance,
-                            max_items_per_instance, order, items, cap, n_out);
+int wpm_build_queue(const int32_t *k, const float *cost, const int32_t *group, int32_t num,
+                    int32_t cbits, int32_t lanes, int32_t min_items_per_instance,
+                    int32_t max_items_per_instance, int32_t order, wpm_item *items, int64_t cap,
+                    int64_t *n_out, int64_t *items_per_instance) {
+    return wpm::build_queue(k, cost, group, num, cbits, lanes, min_items_per_instance,
+                            max_items_per_instance, order, items, cap, n_out, items_per_instance);
 }
 
 int wpm_pack_bins(const wpm_item *items, int64_t n, const float *cost, int32_t bins,
@@ -74,6 +76,10 @@ int wpm_enumerate(const wpm_batch *batch, const wpm_sched *sched, uint64_t *d_su
 
 int wpm_persistent_grid(const wpm_batch *batch, int32_t wg_size, int32_t *grid) {
     return wpm::persistent_grid(batch, wg_size, grid);
+}
+
+int wpm_valu_probe(int op, int waves_per_simd, int iters, double *lane_ops_per_s) {
+    return wpm::valu_probe_run(op, waves_per_simd, iters, lane_ops_per_s);
 }
 
 int wpm_device_query(int32_t *num_cus, int64_t *wallclock_khz, int32_t *lds_per_block) {

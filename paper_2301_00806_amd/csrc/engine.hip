@@ -149,6 +149,9 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     a.stats = (unsigned long long *)d_stats;
     a.times = s->d_item_times;
     a.bins = s->d_bin_offsets;
+    // persistent workgroups reserve output slots in chunks (few global
+    // atomics); one-shot workgroups of the plain mode reserve exactly
+    a.chunk = (s->mode == WPM_SCHED_PLAIN) ? 0 : 128;
     const dim3 block((unsigned)s->wg_size);
     if (s->mode == WPM_SCHED_PLAIN) {
         // One launch per instance: a grid of exactly that instance's items.

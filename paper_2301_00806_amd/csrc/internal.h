@@ -49,9 +49,10 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
                   wpm_instance_info *info);
 void cost_features(const wpm_instance_info &info, const Incidence &inc,
                    const std::vector<int32_t> &crit, float *out);
-int build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits, int32_t lanes,
-                int32_t min_items_per_instance, int32_t max_items_per_instance, int32_t order,
-                wpm_item *items, int64_t cap, int64_t *n_out);
+int build_queue(const int32_t *k, const float *cost, const int32_t *group, int32_t num,
+                int32_t cbits, int32_t lanes, int32_t min_items_per_instance,
+                int32_t max_items_per_instance, int32_t order, wpm_item *items, int64_t cap,
+                int64_t *n_out, int64_t *items_per_instance);
 
 int pack_bins(const wpm_item *items, int64_t n, const float *cost, int32_t bins,
               wpm_item *out_items, int64_t *out_offsets, double *max_load);

@@ -15,20 +15,24 @@
 
 namespace wpm {
 
-int build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits, int32_t lanes,
-                int32_t min_items_per_instance, int32_t max_items_per_instance, int32_t order,
-                wpm_item *items, int64_t cap, int64_t *n_out) {
+int build_queue(const int32_t *k, const float *cost, const int32_t *group, int32_t num,
+                int32_t cbits, int32_t lanes, int32_t min_items_per_instance,
+                int32_t max_items_per_instance, int32_t order, wpm_item *items, int64_t cap,
+                int64_t *n_out, int64_t *items_per_instance) {
     if (!k || !n_out || num < 0 || lanes < 1 || lanes > 1024 || cbits < 0 || order < 0 ||
         order > 1)
         return WPM_EINVAL;
-    struct Tmp {
-        wpm_item it;
-        double cost;
+    struct Inst {
+        int32_t i, c, grp;
+        uint64_t ni, chunks;
+        double item_cost;  // cost of one full item
     };
-    std::vector<Tmp> out;
+    std::vector<Inst> v;
+    v.reserve(num);
     int64_t total = 0;
     for (int i = 0; i < num; ++i) {
         if (k[i] < 0 || k[i] > WPM_MAX_K) return WPM_EINVAL;
+        if (items_per_instance) items_per_instance[i] = 0;
         // k = 0: the only kernel vector is x = 0, the empty complex, which is
         // never a result; the instance needs no sweep.
         if (k[i] == 0) continue;
@@ -49,26 +53,33 @@ int build_queue(const int32_t *k, const float *cost, int32_t num, int32_t cbits,
         const uint64_t ni = n_items(c);
         if (ni > (uint64_t)(INT64_MAX / 4)) return WPM_ELIMIT;
         total += (int64_t)ni;
-        if (total > cap || !items) continue;
+        if (items_per_instance) items_per_instance[i] = (int64_t)ni;
         const uint64_t chunks = 1ull << (kp - c);
         const double cv = cost ? (double)cost[i] : 1.0;
-        for (uint64_t q = 0; q < ni; ++q) {
-            Tmp t;
-            t.it.instance = (uint32_t)i;
-            t.it.cbits = (uint16_t)c;
-            const uint64_t first = q * (uint64_t)lanes;
-            t.it.lanes = (uint16_t)std::min<uint64_t>((uint64_t)lanes, chunks - first);
-            t.it.first = first;
-            t.cost = cv * (double)t.it.lanes * std::ldexp(1.0, c);
-            out.push_back(t);
-        }
+        v.push_back({i, c, group ? group[i] : 0, ni, chunks,
+                     cv * (double)std::min<uint64_t>((uint64_t)lanes, chunks) * std::ldexp(1.0, c)});
     }
     *n_out = total;
     if (total > cap || !items) return WPM_ECAP;
-    if (order == 1)
-        std::stable_sort(out.begin(), out.end(),
-                         [](const Tmp &a, const Tmp &b) { return a.cost > b.cost; });
-    for (size_t i = 0; i < out.size(); ++i) items[i] = out[i].it;
+    // Groups in decreasing key order; inside a group, instance order or
+    // decreasing item cost.  All full items of an instance cost the same, so
+    // instance-major emission in cost order is longest-processing-time-first
+    // up to the partial last items.
+    std::stable_sort(v.begin(), v.end(), [&](const Inst &a, const Inst &b) {
+        if (a.grp != b.grp) return a.grp > b.grp;
+        return order == 1 && a.item_cost > b.item_cost;
+    });
+    int64_t w = 0;
+    for (const Inst &in : v) {
+        for (uint64_t q = 0; q < in.ni; ++q) {
+            wpm_item &it = items[w++];
+            it.instance = (uint32_t)in.i;
+            it.cbits = (uint16_t)in.c;
+            const uint64_t first = q * (uint64_t)lanes;
+            it.lanes = (uint16_t)std::min<uint64_t>((uint64_t)lanes, in.chunks - first);
+            it.first = first;
+        }
+    }
     return WPM_OK;
 }
 

@@ -36,7 +36,6 @@
 namespace wpm {
 
 constexpr int DEV_HDR_WORDS = 16;  // must match the host packer's header size
-constexpr int WPM_OUT_CHUNK = 128;  // record slots a wave reserves at a time (>= 64)
 enum {
     D_K = 1, D_KP = 2, D_M = 3, D_W = 4, D_G = 5, D_QS = 6, D_RS = 7, D_MAXF = 8
 };
@@ -53,6 +52,7 @@ struct KArgs {
     unsigned long long *stats;
     uint64_t *times;
     const int64_t *bins;  // mode 3: [grid + 1] item ranges per workgroup
+    uint64_t chunk;       // record slots a wave reserves at a time (0: exactly what it needs)
     int mode;  // 0 direct (one item per workgroup), 1 static stride, 2 dynamic queue, 3 packed bins
     int pad;
 };
@@ -287,16 +287,17 @@ __global__ __launch_bounds__(512) void sweep_kernel(const uint32_t *__restrict__
                             if (out_pos + nb > out_end) {
                                 // close the current chunk with sentinel
                                 // records and reserve a new one (one global
-                                // atomic per WPM_OUT_CHUNK record slots)
+                                // atomic per a.chunk record slots)
                                 for (uint64_t e0 = out_pos + (uint64_t)lane; e0 < out_end && e0 < a.cap;
                                      e0 += 64) {
                                     a.surv[2 * e0] = 0;
                                     a.surv[2 * e0 + 1] = ~0ull;
                                 }
+                                const uint64_t want = a.chunk > nb ? a.chunk : nb;
                                 unsigned long long base = 0;
-                                if (lane == 0) base = atomicAdd(a.slots, (unsigned long long)WPM_OUT_CHUNK);
+                                if (lane == 0) base = atomicAdd(a.slots, (unsigned long long)want);
                                 out_pos = rfl64(base);
-                                out_end = out_pos + WPM_OUT_CHUNK;
+                                out_end = out_pos + want;
                             }
                             if (ok) {
                                 const uint32_t rk = __builtin_amdgcn_mbcnt_hi(

@@ -141,6 +141,13 @@ def prepare_many(insts, seed: int = 0, threads: int = _POOL_THREADS) -> List[Pre
         return list(ex.map(one, enumerate(insts)))
 
 
+def valu_probe(op: int = 0, waves_per_simd: int = 4, iters: int = 20000) -> float:
+    """Measured 32-bit integer lane-ops/s of the device (see wpm_valu_probe)."""
+    v = ctypes.c_double(0)
+    L.check("wpm_valu_probe", L.lib().wpm_valu_probe(op, waves_per_simd, iters, ctypes.byref(v)))
+    return v.value
+
+
 def device_query():
     cus = ctypes.c_int32(0)
     clk = ctypes.c_int64(0)
@@ -148,6 +155,9 @@ def device_query():
     L.check("wpm_device_query", L.lib().wpm_device_query(ctypes.byref(cus), ctypes.byref(clk),
                                                          ctypes.byref(lds)))
     return cus.value, clk.value, lds.value
+
+
+ITEM_DTYPE = np.dtype([("instance", "<u4"), ("cbits", "<u2"), ("lanes", "<u2"), ("first", "<u8")])
 
 
 def _gm(groups: int) -> int:
@@ -205,24 +215,29 @@ class DeviceBatch:
 
 def build_queue(k: np.ndarray, cbits: int, lanes: int, cost: Optional[np.ndarray] = None,
                 max_items_per_instance: int = 0, order: int = 0,
-                min_items_per_instance: int = 1) -> np.ndarray:
+                min_items_per_instance: int = 1, group: Optional[np.ndarray] = None,
+                return_counts: bool = False):
+    """Items of a batch (wpm_build_queue).  With `group`, items come out group
+    by group in decreasing group key; return_counts adds the items per instance."""
     lib = L.lib()
     ka = np.ascontiguousarray(k, dtype=np.int32)
     ca = None if cost is None else np.ascontiguousarray(cost, dtype=np.float32)
+    ga = None if group is None else np.ascontiguousarray(group, dtype=np.int32)
     n = ctypes.c_int64(0)
     cp = None if ca is None else _ptr(ca, L.c_f32p)
-    st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, len(ka), cbits, lanes, min_items_per_instance,
-                             max_items_per_instance, order, None, 0, ctypes.byref(n))
+    gp = None if ga is None else _ptr(ga, L.c_i32p)
+    per = np.zeros(max(1, len(ka)), dtype=np.int64)
+    st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, gp, len(ka), cbits, lanes, min_items_per_instance,
+                             max_items_per_instance, order, None, 0, ctypes.byref(n), None)
     L.check("wpm_build_queue", st, (L.WPM_ECAP, L.WPM_OK))
-    items = (L.Item * max(1, n.value))()
-    st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, len(ka), cbits, lanes, min_items_per_instance,
-                             max_items_per_instance, order, items, n.value, ctypes.byref(n))
+    arr = np.zeros(max(1, n.value), dtype=ITEM_DTYPE)
+    st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, gp, len(ka), cbits, lanes, min_items_per_instance,
+                             max_items_per_instance, order,
+                             arr.ctypes.data_as(ctypes.POINTER(L.Item)), n.value, ctypes.byref(n),
+                             _ptr(per, L.c_i64p))
     L.check("wpm_build_queue", st)
-    arr = np.frombuffer(items, dtype=ITEM_DTYPE, count=n.value).copy()
-    return arr
-
-
-ITEM_DTYPE = np.dtype([("instance", "<u4"), ("cbits", "<u2"), ("lanes", "<u2"), ("first", "<u8")])
+    arr = arr[:n.value]
+    return (arr, per[:len(ka)]) if return_counts else arr
 
 
 def pack_bins(items: np.ndarray, bins: int, cost: Optional[np.ndarray] = None):
@@ -266,14 +281,30 @@ def split_by_class(batch: "DeviceBatch", items: np.ndarray):
     if len(items) == 0:
         return items, []
     c = batch.cls[items["instance"].astype(np.int64)]
-    codes = sorted(np.unique(c), reverse=True)
-    out, segs, pos = [], [], 0
-    for code in codes:
-        sel = items[c == code]
-        out.append(sel)
-        segs.append(Segment(int(code), pos, pos + len(sel)))
-        pos += len(sel)
-    return np.concatenate(out), segs
+    order = np.argsort(-c, kind="stable")
+    items = items[order]
+    c = c[order]
+    cuts = np.flatnonzero(np.diff(c)) + 1
+    starts = np.concatenate([[0], cuts])
+    ends = np.concatenate([cuts, [len(items)]])
+    return items, [Segment(int(c[a]), int(a), int(b)) for a, b in zip(starts, ends)]
+
+
+def class_items(batch: "DeviceBatch", cbits: int, lanes: int, cost: Optional[np.ndarray] = None,
+                order: int = 0, min_items_per_instance: int = 1, max_items_per_instance: int = 0):
+    """Items grouped by template class (largest first) straight from the
+    builder, with their segments: one launch per class."""
+    items, per = build_queue(batch.k, cbits, lanes, cost=cost, order=order,
+                             min_items_per_instance=min_items_per_instance,
+                             max_items_per_instance=max_items_per_instance,
+                             group=batch.cls, return_counts=True)
+    segs, pos = [], 0
+    for code in sorted(np.unique(batch.cls), reverse=True):
+        n = int(per[batch.cls == code].sum())
+        if n:
+            segs.append(Segment(int(code), pos, pos + n))
+            pos += n
+    return items, segs
 
 
 @dataclass
@@ -328,13 +359,22 @@ class Sweeper:
         self._times = (torch.zeros((max(1, len(items)), 2), dtype=torch.int64, device=self.surv.device)
                        if want_times else None)
 
-    def launch(self, mode: int, wg_size: int = 256, grid: int = 0, stream=None) -> None:
+    def launch(self, mode: int, wg_size: int = 256, grid: int = 0, stream=None,
+               seg_events: bool = False) -> None:
+        """One wpm_enumerate call per segment, in order, on `stream`.  With
+        seg_events, HIP events bracket each segment's launch on that stream
+        (self.seg_events: list of (class, start event, end event))."""
         torch = self.torch
         if stream is None:
             stream = torch.cuda.current_stream()
         items = self._items_host
         segs = self._segments or [Segment(None, 0, 0)]
+        self.seg_events = []
         for i, sg in enumerate(segs):
+            if seg_events:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
             cb = self.batch.c_batch if sg.cls is None else self.batch.class_batches[sg.cls]
             n = sg.end - sg.start
             bins = self._seg_bins[i] if self._segments else None
@@ -352,6 +392,9 @@ class Sweeper:
                                        self.cap, self.counts.data_ptr(), self.total.data_ptr(),
                                        self.stats.data_ptr(), ctypes.c_void_p(stream.cuda_stream))
             L.check("wpm_enumerate", st)
+            if seg_events:
+                e1.record(stream)
+                self.seg_events.append((sg.cls, e0, e1))
 
     def fetch_records(self, n: Optional[int] = None):
         """Copy the first n record slots (default: all used slots) into a

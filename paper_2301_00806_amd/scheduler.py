@@ -41,9 +41,13 @@ def per_vector_cost(model, features: np.ndarray) -> np.ndarray:
     return np.exp(np.clip(y[:, 0], -20.0, 20.0)).astype(np.float32)
 
 
-def _group(batch, items, split: bool):
+def _items(batch, split: bool, cbits: int, wg: int, cost=None, order: int = 0,
+           min_items: int = 1):
     if split:
-        return E.split_by_class(batch, items)
+        return E.class_items(batch, cbits, wg, cost=cost, order=order,
+                             min_items_per_instance=min_items)
+    items = E.build_queue(batch.k, cbits, wg, cost=cost, order=order,
+                          min_items_per_instance=min_items)
     return items, [E.Segment(None, 0, len(items))]
 
 
@@ -52,16 +56,14 @@ def make_plan(batch: "E.DeviceBatch", policy: str, cost: Optional[np.ndarray] = 
               split: bool = True) -> Plan:
     """Items for a policy; with `split`, grouped by kernel template class
     (one launch per class), else one launch under the batch's largest template."""
-    k = batch.k
     if policy == "plain":
-        items = E.build_queue(k, cbits, wg, min_items_per_instance=plain_min_items)
-        items, segs = _group(batch, items, split)
+        items, segs = _items(batch, split, cbits, wg, min_items=plain_min_items)
         return Plan(policy, L.SCHED_PLAIN, items, segs)
     if policy == "static":
-        items, segs = _group(batch, E.build_queue(k, cbits, wg), split)
+        items, segs = _items(batch, split, cbits, wg)
         return Plan(policy, L.SCHED_STATIC, items, segs)
-    c = np.ones(len(k), np.float32) if cost is None else np.asarray(cost, np.float32)
-    items, segs = _group(batch, E.build_queue(k, cbits, wg, cost=c, order=1), split)
+    c = np.ones(len(batch.k), np.float32) if cost is None else np.asarray(cost, np.float32)
+    items, segs = _items(batch, split, cbits, wg, cost=c, order=1)
     if policy == "dynamic":
         return Plan(policy, L.SCHED_DYNAMIC, items, segs)
     if policy == "packed":

@@ -171,3 +171,15 @@ def test_template_class_split_keeps_every_item():
     assert [s.cls for s in segs] == [80416, 40416, 20416]
     for s in segs:
         assert set(FakeBatch.cls[out[s.start:s.end]["instance"]]) == {s.cls}
+
+
+def test_build_queue_groups_and_counts():
+    k = np.array([9, 12, 16, 8, 0, 20], dtype=np.int32)
+    grp = np.array([1, 3, 1, 2, 3, 3], dtype=np.int32)
+    items, per = E.build_queue(k, 9, 64, cost=np.arange(1, 7, dtype=np.float32), order=1,
+                               group=grp, return_counts=True)
+    g = grp[items["instance"].astype(np.int64)]
+    assert list(g) == sorted(g, reverse=True)          # groups in decreasing key
+    assert per[4] == 0 and per.sum() == len(items)
+    for i in range(len(k)):
+        assert (items["instance"] == i).sum() == per[i]
