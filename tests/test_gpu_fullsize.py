@@ -1,0 +1,121 @@
+"""Parity at the benchmark's full size, in the launch configuration bench.py
+times: the 16384-instance learned-scheduler batch, one persistent launch per
+kernel template class, dynamic queue, 12 chunk bits, 256-thread workgroups.
+
+  - every instance with 1 <= k <= 10, and a sample across every larger k (up to
+    the k = 34 maximum of the batch), compared set for set with the oracle;
+  - a random sample of survivor records, from all instances, checked by the
+    oracle's verifier from their facet lists alone;
+  - the counts agree with the total, and with a second schedule (static).
+"""
+import os
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle as O
+import wpm_inputs as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def kvec(p, xs):
+    """Facet bit vectors K = sum_t x_t K_t (rows of W uint32) of kernel vectors x."""
+    xs = np.asarray(xs, dtype=np.uint64)
+    K = np.zeros((len(xs), p.W), dtype=np.uint32)
+    for t in range(p.k):
+        sel = ((xs >> np.uint64(t)) & np.uint64(1)).astype(bool)
+        K[sel] ^= p.basis[t]
+    return K
+
+
+def kvec_of_sets(p, sets):
+    """The same bit vectors for lists of facet masks (the oracle's output)."""
+    pos = {int(f): j for j, f in enumerate(p.facets)}
+    K = np.zeros((len(sets), p.W), dtype=np.uint32)
+    for r, S in enumerate(sets):
+        for f in S:
+            j = pos[f]
+            K[r, j // 32] |= np.uint32(1 << (j % 32))
+    return K
+
+
+def canon(K):
+    return K[np.lexsort(K.T[::-1])] if len(K) else K
+
+
+def facet_list(p, x):
+    K = kvec(p, [x])[0]
+    return [int(p.facets[w * 32 + b]) for w in range(p.W) for b in range(32) if (int(K[w]) >> b) & 1]
+
+
+@pytest.fixture(scope="module")
+def run():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_00806_amd import engine as E, scheduler as S
+    print("[fullsize] building 16384 instances", flush=True)
+    preps = E.prepare_many(W.learned(E.kdim, count=16384))
+    batch = E.DeviceBatch(preps)
+    sw = E.Sweeper(batch, cap=1 << 26)
+    plan = S.make_plan(batch, "dynamic", cbits=12, wg=256)
+    sw.set_items(plan.items, segments=plan.segments)
+    print(f"[fullsize] sweeping {batch.vectors:.3e} vectors", flush=True)
+    sw.launch(plan.mode, wg_size=256)
+    res = sw.result()
+    rec = sw.fetch_records().copy()
+    rec = rec[rec[:, 1] != -1]
+    return E, S, preps, batch, sw, res, rec
+
+
+def test_counts_total_and_schedule_invariance(run):
+    E, S, preps, batch, sw, res, rec = run
+    assert int(res.counts.sum()) == res.total == len(rec)
+    assert res.total == 54267619
+    plan = S.make_plan(batch, "static", cbits=12, wg=256)
+    sw.set_items(plan.items, segments=plan.segments)
+    sw.launch(plan.mode, wg_size=256)
+    res2 = sw.result()
+    assert np.array_equal(res2.counts, res.counts)
+
+
+def test_sets_match_oracle_small_and_sampled(run):
+    E, S, preps, batch, sw, res, rec = run
+    ks = np.array([p.k for p in preps])
+    rng = np.random.default_rng(11)
+    chosen = list(np.flatnonzero((ks >= 1) & (ks <= 10)))
+    for k in sorted(set(ks[ks > 14])):
+        idx = np.flatnonzero(ks == k)
+        chosen += list(rng.choice(idx, size=min(3, len(idx)), replace=False))
+    print(f"[fullsize] oracle on {len(chosen)} instances", flush=True)
+    order = np.argsort(rec[:, 1], kind="stable")
+    rs = rec[order]
+    starts = np.searchsorted(rs[:, 1], np.arange(len(preps)))
+    ends = np.searchsorted(rs[:, 1], np.arange(len(preps)), side="right")
+
+    def one(i):
+        p = preps[i]
+        want = O.enumerate_wpm(p.n, [int(f) for f in p.facets], p.max_facets)
+        got = canon(kvec(p, rs[starts[i]:ends[i], 0].astype(np.uint64)))
+        ref = canon(kvec_of_sets(p, want))
+        return i, got.shape == ref.shape and np.array_equal(got, ref), len(want)
+
+    with ThreadPoolExecutor(THREADS) as ex:
+        for i, ok, n in ex.map(one, chosen):
+            assert ok, f"instance {i} (k={preps[i].k}) differs from the oracle ({n} expected)"
+            assert int(res.counts[i]) == n
+
+
+def test_sampled_survivors_verify(run):
+    E, S, preps, batch, sw, res, rec = run
+    rng = np.random.default_rng(5)
+    pick = rng.choice(len(rec), size=20000, replace=False)
+    for r in pick:
+        x, i = int(rec[r, 0]), int(rec[r, 1])
+        p = preps[i]
+        assert O.verify(p.n, facet_list(p, x), [int(f) for f in p.facets], p.max_facets), (i, x)
