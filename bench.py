@@ -33,7 +33,7 @@ def log(msg: str) -> None:
 # every 2 clocks on each of 4 SIMDs, the same issue rate as fp32 FMA behind the
 # 157.3 TFLOP/s figure) x 2.4 GHz.  wpm_valu_probe measures it on the device.
 INT32_PEAK = 256 * 128 * 2.4e9
-ALG_OPS_PER_VECTOR = 8             # fast filter: 4 XOR + 3 threshold ops + 1 compare
+ALG_OPS_PER_VECTOR = 7             # fast filter: 4 XOR + 2 threshold ops + 1 compare
 
 
 def build_workload(count: int, seed_start: int = 0):

@@ -12,6 +12,7 @@ namespace wpm {
 // RS words, one per basis vector t (rows t >= k are zero):
 //   [0, 4)                 slot words of the fast-filter group (<= 32 ridges)
 //   [4, 4 + (G-1) QS)      slot words of groups 1..G-1, QS words per group
+//                          (4-word groups stored as (a, a^b, c, c^d))
 //   [4 + (G-1) QS, +W)     the basis vector itself as facet words
 constexpr uint32_t WPM_TABLE_MAGIC = 0x314D5057u;  // "WPM1"
 constexpr int WPM_HDR_WORDS = 16;

@@ -431,6 +431,19 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
         const int g = 1 + (int)(i / 32), b = (int)(i % 32);
         place(rest[i], 4 + (g - 1) * QS, b, QS);
     }
+    // A group of 4 slot words (a, b, c, d) is stored as (a, a^b, c, c^d): an
+    // invertible linear change of coordinates, so Gray-code XOR updates still
+    // apply, under which "at least 3 of a, b, c, d" takes two 3-input logic ops.
+    auto transform4 = [&](int base) {
+        for (int t = 0; t < k; ++t) {
+            uint32_t *r = rows + (size_t)t * RS + base;
+            r[1] ^= r[0];
+            r[3] ^= r[2];
+        }
+    };
+    transform4(0);
+    if (QS == 4)
+        for (int g = 1; g < G; ++g) transform4(4 + (g - 1) * QS);
     const int koff = 4 + (G - 1) * QS;
     for (int t = 0; t < k; ++t)
         for (int w = 0; w < W; ++w) rows[(size_t)t * RS + koff + w] = basis[(size_t)t * W + w];

@@ -13,8 +13,8 @@
 // its first p-1 parent bits are set).  Work is split in two phases per block
 // of 64 steps:
 //   phase 1  the fast filter: 32 ridges in 4 slot words held in VGPRs,
-//            updated by 4 XORs and tested by 3 bit-logic ops per step;
-//            the steps where some lane passes are recorded in a 64-bit mask.
+//            updated by 4 XORs and tested by 2 bit-logic ops per step; the
+//            steps where some lane passes are recorded in a 64-bit mask.
 //   phase 2  for each recorded step only: the lane's state is rebuilt as
 //            P ^ U[v], where P (per lane, VGPRs) is the contribution of the
 //            basis vectors above bit 6 and U (LDS, 64 rows staged per
@@ -57,15 +57,14 @@ struct KArgs {
     int pad;
 };
 
-__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
-}
-__device__ __forceinline__ uint32_t and3(uint32_t a, uint32_t b, uint32_t c) {
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x80);
-}
-// Per ridge bit: at least 3 of the 4 slot words set.
-__device__ __forceinline__ uint32_t fail4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
-    return (d & maj3(a, b, c)) | and3(a, b, c);
+// Per ridge bit: at least 3 of the slot bits (a, b, c, d) set, given the
+// stored words a, u = a^b, c, v = c^d.  Counting a + b = 2a when u = 0 and 1
+// when u = 1 (likewise for c, d), the test is (u | a) & ~(u & v) & (v | c):
+// two 3-input logic ops (v_bitop3; operand i is truth-table input 0xF0, 0xCC,
+// 0xAA for i = 0, 1, 2).
+__device__ __forceinline__ uint32_t fail4(uint32_t a, uint32_t u, uint32_t c, uint32_t v) {
+    const uint32_t t = __builtin_amdgcn_bitop3_b32(u, a, v, 0x5C);  // (u | a) & ~(u & v)
+    return __builtin_amdgcn_bitop3_b32(t, v, c, 0xE0);                // t & (v | c)
 }
 
 template <int QS>
@@ -218,8 +217,10 @@ __global__ __launch_bounds__(512) void sweep_kernel(const uint32_t *__restrict__
             const int koff = 4 + (G - 1) * mqs;
             for (uint64_t blk = 0; blk < nblk; ++blk) {
                 // ---- phase 1: fast filter over 64 Gray steps.  The step mask
-                // is set on a rarely taken branch, so a step costs 8 VALU ops
-                // and one conditional branch.
+                // is set on a rarely taken branch, so a step costs 7 VALU ops
+                // and one conditional branch.  (Testing pairs of steps with one
+                // branch was measured slower: every fired pair costs phase 2 a
+                // second step, and phase 2 is LDS-latency bound.)
                 uint64_t fire = 0;
 #pragma unroll
                 for (int s = 0; s < 64; ++s) {

@@ -42,12 +42,19 @@ def state(R, x):
     return v
 
 
+def slots4(v, base):
+    """4-word groups are stored as (a, a^b, c, c^d)."""
+    a, u, c, w = v[base], v[base + 1], v[base + 2], v[base + 3]
+    return [a, a ^ u, c, c ^ w]
+
+
 def accept(h, v):
-    if at_least3([v[0], v[1], v[2], v[3]]) != 0:
+    if at_least3(slots4(v, 0)) != 0:
         return False
     for g in range(1, h["G"]):
         base = 4 + (g - 1) * h["QS"]
-        if at_least3([v[base + q] for q in range(h["QS"])]) != 0:
+        words = slots4(v, base) if h["QS"] == 4 else [v[base + q] for q in range(h["QS"])]
+        if at_least3(words) != 0:
             return False
     koff = 4 + (h["G"] - 1) * h["QS"]
     cnt = sum(bin(int(v[koff + w])).count("1") for w in range(h["W"]))
@@ -80,7 +87,7 @@ def survivors_walk(tab, cbits=7):
         for blk in range(1 << (c - 6)):
             fire = []
             for s in range(64):
-                if at_least3(list(s4)) == 0:
+                if at_least3(slots4(s4, 0)) == 0:
                     fire.append(s)
                 if s < 63:
                     t = (s + 1 & -(s + 1)).bit_length() - 1
