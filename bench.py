@@ -7,7 +7,9 @@ one pass of the hot path over the whole batch with the packed tables already
 resident in HBM: cost prediction, queue packing, the persistent sweep of all
 sum_i 2^k_i kernel vectors, and the read-back of the exact per-instance
 counts and survivor records.  The plain schedule (one launch per instance) is
-timed on the same batch for comparison.
+timed on the same batch for comparison, and so is the pruned sweep over a
+convenient kernel basis (Section 2.1: same results, fewer vectors visited),
+reported beside the headline figure.
 
 Prints one JSON line.
 """
@@ -46,6 +48,17 @@ def build_workload(count: int, seed_start: int = 0):
     preps = E.prepare_many(insts)
     log(f"prepared (candidates, basis, packing) in {time.time() - t:.1f}s")
     return insts, preps
+
+
+def oracle_counts_match(counts, n_inst):
+    """Per-instance counts against the oracle's, stored for the 16384-instance
+    workload by tests/golden/make_learned_counts.py (None for other sizes)."""
+    path = os.path.join(ROOT, "tests", "golden", "learned16384_counts.json")
+    if n_inst != 16384 or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        gold = np.array(json.load(f)["counts"], dtype=np.uint64)
+    return bool(np.array_equal(np.asarray(counts, dtype=np.uint64), gold))
 
 
 def cpu_baseline(preps, budget_s: float):
@@ -112,6 +125,10 @@ def main():
     ap.add_argument("--no-split", action="store_true",
                     help="one launch under the largest kernel template instead of one per class")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-pruned", action="store_true",
+                    help="skip the convenient-basis (pruned) sweep of the same batch")
+    ap.add_argument("--min-free", type=int, default=0,
+                    help="free coordinates a pruned instance keeps (0 = engine default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -164,7 +181,7 @@ def main():
         return S.make_plan(batch, args.learned_policy, cost=cost, cbits=args.cbits, wg=args.wg,
                            split=not args.no_split)
 
-    def timed_plan(make, steps, warmup, label):
+    def timed_plan(make, steps, warmup, label, sw=sw, n_inst=len(preps), vec=vectors):
         plan = make()
         for _ in range(warmup):
             sw.set_items(plan.items, segments=plan.segments)
@@ -180,7 +197,7 @@ def main():
             e0.record(stream)
             sw.launch(plan.mode, wg_size=args.wg, stream=stream, seg_events=True)
             e1.record(stream)
-            counts = sw.counts[:len(preps)].cpu()      # synchronises the stream
+            counts = sw.counts[:n_inst].cpu()          # synchronises the stream
             tot, slots = (int(v) for v in sw.total.cpu())
             if slots > sw.cap:
                 raise SystemExit(f"survivor buffer too small: {slots} > {sw.cap}")
@@ -192,7 +209,7 @@ def main():
         wall = (time.perf_counter() - t0) / steps
         res = sw.result()
         log(f"{label}: kernel {np.mean(kern_ms):.2f} ms, step {wall * 1e3:.2f} ms, "
-            f"{vectors / wall:.3e} vectors/s, total WPMs {res.total}, stats {res.stats[:3]}")
+            f"{vec / wall:.3e} vectors/s, total WPMs {res.total}, stats {res.stats[:3]}")
         timed_plan.seg_ms = {c: float(np.mean(v)) for c, v in seg_ms.items()}
         return wall, float(np.mean(kern_ms)), res
 
@@ -226,6 +243,35 @@ def main():
         t_o, k_o, res_o = timed_plan(mk, st, 1, name)
         assert np.array_equal(res_o.counts, res_b.counts), f"{name} counts differ"
         out[name] = {"value": vectors / t_o, "ms_per_step": t_o * 1e3, "kernel_ms": k_o}
+
+    # ---- convenient-basis block pruning: the same batch, the same results,
+    # fewer vectors visited
+    pruned = None
+    if not args.no_pruned:
+        t = time.time()
+        mf = args.min_free or E.DEFAULT_MIN_FREE
+        preps_p = E.prepare_many(insts, prune=True, min_free=mf)
+        prep_s = time.time() - t
+        batch_p = E.DeviceBatch(preps_p)
+        visited = batch_p.visited
+        log(f"pruned: prepared in {prep_s:.1f}s, visits {visited:.4e} of {vectors:.4e} vectors "
+            f"({visited / vectors:.3f})")
+        sw_p = E.Sweeper(batch_p, cap=args.cap)
+        feats_p = CM.features_of(preps_p)
+
+        def plan_pruned():
+            cost = S.per_vector_cost(model, feats_p)
+            return S.make_plan(batch_p, "dynamic", cost=cost, cbits=args.cbits, wg=args.wg,
+                               split=not args.no_split)
+        t_p, k_p, res_p = timed_plan(plan_pruned, args.steps, args.warmup, "pruned-dynamic",
+                                     sw=sw_p, n_inst=len(preps_p), vec=vectors)
+        assert np.array_equal(res_p.counts, res_b.counts), "pruned counts differ"
+        pruned = {"min_free": mf, "visited_vectors": visited, "covered_vectors": vectors,
+                  "ms_per_step": t_p * 1e3, "kernel_ms": k_p,
+                  "covered_per_s": vectors / t_p, "visited_per_s": visited / t_p,
+                  "speedup_vs_learned_step": t_b / t_p, "prep_s": prep_s,
+                  "counts_equal_to_full_sweep": True}
+        del sw_p, batch_p
 
     # model error on the fresh instances: measured per-instance time vs prediction
     _, Tte, _ = S.measure_labels(preps, cbits=args.cbits, wg=args.wg, repeats=1) if not args.only_learned \
@@ -279,8 +325,10 @@ def main():
                    "schedule": f"learned: {args.learned_policy}, LPT on MLP-predicted cost"},
         "wpm_total": int(res_b.total),
         "wpm_counts_sha256": __import__("hashlib").sha256(res_b.counts.tobytes()).hexdigest(),
+        "wpm_counts_match_oracle": oracle_counts_match(res_b.counts, len(preps)),
         "kernel_ms": k_b,
         "schedules": out,
+        "pruned": pruned,
         "cost_model": model_err,
         "autotune": None if tuned is None else {"key": tuned["key"], "cbits": tuned["cbits"],
                                                 "wg": tuned["wg"], "cached": tuned["cached"]},

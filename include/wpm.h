@@ -109,6 +109,59 @@ int wpm_kernel_basis(int n, int m, const uint32_t *facets, int32_t M, uint32_t *
  * C(n+4-ceil(n/2), 4) + C(n+3-floor(n/2), 4).  g(K) > 0 iff |K| <= it. */
 int64_t wpm_ubt_bound(int n);
 
+/* ------------------------------------------------- convenient basis (pruning) */
+
+#define WPM_MAX_BLOCKS 16   /* blocks of a convenient basis */
+#define WPM_MAX_CHOICES 40  /* allowed combinations per block (<= 1 + C(9,2)) */
+
+/*
+ * Block structure of a convenient kernel basis (Section 2.1, the partition
+ * I_1..I_l and the sets X_1..X_l).  Coordinates 0..free_dims-1 of x are
+ * free; block b owns the size[b] coordinates that follow the free ones and
+ * the earlier blocks.  A kernel vector can be a weak pseudo-manifold only if
+ * the part of x on each block is one of that block's allowed combinations
+ * choice[b][0..count[b]-1] (bit j = the block's j-th coordinate), so the
+ * sweep visits 2^free_dims * prod_b count[b] vectors instead of 2^k.
+ */
+typedef struct wpm_blocks {
+    int32_t k;           /* kernel dimension */
+    int32_t free_dims;   /* f: coordinates 0..f-1 are unconstrained */
+    int32_t num_blocks;  /* l (0: no pruning, x ranges over F2^k) */
+    int32_t reserved;
+    int32_t ridge[WPM_MAX_BLOCKS];  /* ridge (index in lexicographic order) defining block b */
+    uint8_t size[WPM_MAX_BLOCKS];   /* q_b, 1..8 */
+    uint8_t count[WPM_MAX_BLOCKS];  /* |X_b| */
+    uint8_t choice[WPM_MAX_BLOCKS][WPM_MAX_CHOICES]; /* allowed local masks, increasing */
+    double log2_vectors; /* log2 of the vectors swept: f + sum_b log2 count[b] */
+} wpm_blocks;
+
+/*
+ * Convenient basis of ker_F2 A(F) by column elimination on the rows of the
+ * basis at the parents of chosen ridges (Section 2.1).  Ridges with 4..9
+ * parents are taken greedily (more parents first, then lexicographic order)
+ * when their parent sets are disjoint from the earlier blocks', when
+ * eliminating on them among the still-free generators leaves every earlier
+ * block generator zero on those parents (so earlier blocks keep their form),
+ * and when they prune something.  For each block the allowed set is computed
+ * exactly: the combinations of the block's generators whose restriction to
+ * the ridge's parents has weight <= 2 (that is, (AK)_r in {0,2}, Proposition
+ * 2.1).  With m - n + 1 parents spanning all even patterns this is the
+ * paper's Z_{m-n} block with at most two generators combined,
+ * 1 + (m-n) + C(m-n, 2) choices.  Every weak pseudo-manifold lies in the
+ * product, so the result set of a sweep is unchanged.
+ *   facets[M], basis[k*W]  as from wpm_kernel_basis (any basis of ker A)
+ *   min_free               keep at least this many free coordinates (a sweep
+ *                          needs >= 7: one lane walks 2^7-aligned Gray chunks);
+ *                          0 gives the most pruning, for counting
+ *   basis_out[k*W]         receives the convenient basis: the free generators,
+ *                          then block 0, block 1, ... (same span as basis)
+ *   blocks                 receives the structure above
+ * x in the new coordinates describes K = sum_t x_t basis_out_t, as before.
+ * Returns WPM_EKMAX if k > 64.
+ */
+int wpm_convenient_basis(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
+                         int32_t k, int32_t min_free, uint32_t *basis_out, wpm_blocks *blocks);
+
 /* Summary of a packed instance. */
 typedef struct wpm_instance_info {
     int32_t n, m, M, N, k;
@@ -128,7 +181,10 @@ typedef struct wpm_instance_info {
 /*
  * Pack one instance for the GPU sweep: selects the fast-filter ridges and lays
  * out the bit-sliced ridge-slot rows and facet rows of every basis vector.
- *   facets[M], basis[k*W]  as returned by the two calls above
+ *   facets[M], basis[k*W]  as returned by the calls above
+ *   blocks                 NULL, or the structure of a convenient basis passed
+ *                          as `basis`: the ridges are then ranked on vectors
+ *                          drawn from the pruned set the sweep will visit
  *   max_facets             bound on |K| (0 = none; the paper applies
  *                          wpm_ubt_bound(n) when m = n + 4, Algorithm 4.4)
  *   seed                   seeds the sampling that ranks ridges (any value;
@@ -139,8 +195,8 @@ typedef struct wpm_instance_info {
  * ridge's parent count exceeds the WPM_MAX_* limits.
  */
 int wpm_pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
-                      int32_t k, int32_t max_facets, uint64_t seed, uint32_t *table,
-                      int64_t cap_words, wpm_instance_info *info);
+                      int32_t k, const wpm_blocks *blocks, int32_t max_facets, uint64_t seed,
+                      uint32_t *table, int64_t cap_words, wpm_instance_info *info);
 
 /* ------------------------------------------------------------ scheduling */
 
@@ -186,6 +242,26 @@ int wpm_build_queue(const int32_t *k, const float *cost, const int32_t *group, i
                     int32_t cbits, int32_t lanes, int32_t min_items_per_instance,
                     int32_t max_items_per_instance, int32_t order, wpm_item *items, int64_t cap,
                     int64_t *n_out, int64_t *items_per_instance);
+
+/*
+ * Items of a pruned sweep (Section 2.1: the product X_1 x ... x X_l of the
+ * blocks' allowed sets times the free coordinates).  Arguments as for
+ * wpm_build_queue, with blocks[num] in place of k (blocks[i].k is the kernel
+ * dimension).  For each allowed block tuple with high part h (bits f..k-1 of
+ * x), the items cover the Gray indices [g^-1(h) 2^f, (g^-1(h) + 1) 2^f),
+ * g^-1 the inverse Gray code: exactly the 2^f vectors with that high part.
+ * Tuples come in mixed-radix order, block 0 fastest; an item never spans two
+ * tuples.  An instance with num_blocks = 0 gets the items wpm_build_queue
+ * gives it.  Requires free_dims >= 7 when num_blocks > 0 (WPM_EINVAL).  For
+ * a pruned instance cbits is clamped to [7, free_dims] and lowered to
+ * free_dims - ceil(log2 lanes) (not below 7), so that one tuple fills whole
+ * workgroups; the min/max item rules then apply to the instance's total.
+ */
+int wpm_build_pruned_queue(const wpm_blocks *blocks, const float *cost, const int32_t *group,
+                           int32_t num, int32_t cbits, int32_t lanes,
+                           int32_t min_items_per_instance, int32_t max_items_per_instance,
+                           int32_t order, wpm_item *items, int64_t cap, int64_t *n_out,
+                           int64_t *items_per_instance);
 
 /*
  * Pack items into `bins` workgroup bins by longest-processing-time-first:

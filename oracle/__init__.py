@@ -164,6 +164,19 @@ def enumerate_wpm(n: int, facets: Sequence[int], max_facets: int = 0,
     return sorted(res)
 
 
+def count_wpm(n: int, facets: Sequence[int], max_facets: int = 0) -> int:
+    """Number of weak pseudo-manifolds enumerate_wpm would list (the same
+    search, counting only)."""
+    arr, p = _u32(facets)
+    ln = ctypes.c_int64(0)
+    cnt = ctypes.c_int64(0)
+    st = lib().or_enumerate(n, p, len(facets), max_facets, None, 0, ctypes.byref(ln),
+                            ctypes.byref(cnt), 0, None)
+    if st != OR_OK:
+        raise ValueError(f"oracle status {st}")
+    return int(cnt.value)
+
+
 def bruteforce_wpm(n: int, facets: Sequence[int], max_facets: int = 0) -> List[Tuple[int, ...]]:
     """Same set as enumerate_wpm, by checking all 2^M subsets (M <= 40)."""
     st, cnt, res = _run(lib().or_bruteforce, n, facets, max_facets)

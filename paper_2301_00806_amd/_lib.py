@@ -19,6 +19,18 @@ c_u64p = ctypes.POINTER(ctypes.c_uint64)
 c_f32p = ctypes.POINTER(ctypes.c_float)
 
 
+MAX_BLOCKS, MAX_CHOICES = 16, 40
+
+
+class Blocks(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("free_dims", ctypes.c_int32),
+                ("num_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ridge", ctypes.c_int32 * MAX_BLOCKS), ("size", ctypes.c_uint8 * MAX_BLOCKS),
+                ("count", ctypes.c_uint8 * MAX_BLOCKS),
+                ("choice", (ctypes.c_uint8 * MAX_CHOICES) * MAX_BLOCKS),
+                ("log2_vectors", ctypes.c_double)]
+
+
 class InstanceInfo(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
                 ("n", "m", "M", "N", "k", "W", "n_crit", "groups", "slots", "n_filter",
@@ -96,12 +108,22 @@ def lib():
     L.wpm_ubt_bound.argtypes = [ctypes.c_int]
     L.wpm_pack_instance.restype = ctypes.c_int
     L.wpm_pack_instance.argtypes = [ctypes.c_int, ctypes.c_int, c_u32p, ctypes.c_int32, c_u32p,
-                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, c_u32p,
-                                    ctypes.c_int64, ctypes.POINTER(InstanceInfo)]
+                                    ctypes.c_int32, ctypes.POINTER(Blocks), ctypes.c_int32,
+                                    ctypes.c_uint64, c_u32p, ctypes.c_int64,
+                                    ctypes.POINTER(InstanceInfo)]
+    L.wpm_convenient_basis.restype = ctypes.c_int
+    L.wpm_convenient_basis.argtypes = [ctypes.c_int, ctypes.c_int, c_u32p, ctypes.c_int32, c_u32p,
+                                       ctypes.c_int32, ctypes.c_int32, c_u32p,
+                                       ctypes.POINTER(Blocks)]
     L.wpm_build_queue.restype = ctypes.c_int
     L.wpm_build_queue.argtypes = [c_i32p, c_f32p, c_i32p, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.POINTER(Item), ctypes.c_int64, c_i64p, c_i64p]
+    L.wpm_build_pruned_queue.restype = ctypes.c_int
+    L.wpm_build_pruned_queue.argtypes = [ctypes.POINTER(Blocks), c_f32p, c_i32p, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Item),
+                                         ctypes.c_int64, c_i64p, c_i64p]
     L.wpm_pack_bins.restype = ctypes.c_int
     L.wpm_pack_bins.argtypes = [ctypes.POINTER(Item), ctypes.c_int64, c_f32p, ctypes.c_int32,
                                 ctypes.POINTER(Item), c_i64p, ctypes.POINTER(ctypes.c_double)]
@@ -141,7 +163,8 @@ def check(call: str, status: int, ok=(WPM_OK,)) -> int:
 
 # Every symbol include/wpm.h declares.
 EXPORTED = ("wpm_strerror", "wpm_last_hip_error", "wpm_build_candidates", "wpm_kernel_basis",
-            "wpm_ubt_bound", "wpm_pack_instance", "wpm_build_queue", "wpm_pack_bins", "wpm_enumerate",
+            "wpm_ubt_bound", "wpm_convenient_basis", "wpm_pack_instance", "wpm_build_queue",
+            "wpm_build_pruned_queue", "wpm_pack_bins", "wpm_enumerate",
             "wpm_device_query", "wpm_persistent_grid", "wpm_valu_probe", "wpm_collect", "wpm_mlp_work_floats", "wpm_mlp_forward",
             "wpm_mlp_grad", "wpm_mlp_adam")
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS, MLP_NORM = 16, 64, 2, 5378, 36

@@ -49,10 +49,16 @@ int wpm_kernel_basis(int n, int m, const uint32_t *facets, int32_t M, uint32_t *
 
 int64_t wpm_ubt_bound(int n) { return wpm::ubt_bound(n); }
 
+int wpm_convenient_basis(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
+                         int32_t k, int32_t min_free, uint32_t *basis_out, wpm_blocks *blocks) {
+    return wpm::convenient_basis(n, m, facets, M, basis, k, min_free, basis_out, blocks);
+}
+
 int wpm_pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
-                      int32_t k, int32_t max_facets, uint64_t seed, uint32_t *table,
-                      int64_t cap_words, wpm_instance_info *info) {
-    return wpm::pack_instance(n, m, facets, M, basis, k, max_facets, seed, table, cap_words, info);
+                      int32_t k, const wpm_blocks *blocks, int32_t max_facets, uint64_t seed,
+                      uint32_t *table, int64_t cap_words, wpm_instance_info *info) {
+    return wpm::pack_instance(n, m, facets, M, basis, k, blocks, max_facets, seed, table,
+                              cap_words, info);
 }
 
 int wpm_build_queue(const int32_t *k, const float *cost, const int32_t *group, int32_t num,
@@ -61,6 +67,16 @@ int wpm_build_queue(const int32_t *k, const float *cost, const int32_t *group, i
                     int64_t *n_out, int64_t *items_per_instance) {
     return wpm::build_queue(k, cost, group, num, cbits, lanes, min_items_per_instance,
                             max_items_per_instance, order, items, cap, n_out, items_per_instance);
+}
+
+int wpm_build_pruned_queue(const wpm_blocks *blocks, const float *cost, const int32_t *group,
+                           int32_t num, int32_t cbits, int32_t lanes,
+                           int32_t min_items_per_instance, int32_t max_items_per_instance,
+                           int32_t order, wpm_item *items, int64_t cap, int64_t *n_out,
+                           int64_t *items_per_instance) {
+    return wpm::build_pruned_queue(blocks, cost, group, num, cbits, lanes, min_items_per_instance,
+                                   max_items_per_instance, order, items, cap, n_out,
+                                   items_per_instance);
 }
 
 int wpm_pack_bins(const wpm_item *items, int64_t n, const float *cost, int32_t bins,

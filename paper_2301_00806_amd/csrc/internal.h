@@ -46,14 +46,21 @@ int build_candidates(int n, int m, const uint32_t *lambda, uint32_t *facets, int
 int kernel_basis(int n, int m, const uint32_t *facets, int32_t M, uint32_t *ridges_out,
                  int32_t cap_r, int32_t *N_out, uint32_t *basis, int32_t cap_k, int32_t *k_out);
 int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
-                  int32_t k, int32_t max_facets, uint64_t seed, uint32_t *table, int64_t cap_words,
-                  wpm_instance_info *info);
+                  int32_t k, const wpm_blocks *blocks, int32_t max_facets, uint64_t seed,
+                  uint32_t *table, int64_t cap_words, wpm_instance_info *info);
+int convenient_basis(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
+                     int32_t k, int32_t min_free, uint32_t *basis_out, wpm_blocks *blocks);
+int validate_blocks(const wpm_blocks &b, int32_t k);
 void cost_features(const wpm_instance_info &info, const Incidence &inc,
                    const std::vector<int32_t> &crit, float *out);
 int build_queue(const int32_t *k, const float *cost, const int32_t *group, int32_t num,
                 int32_t cbits, int32_t lanes, int32_t min_items_per_instance,
                 int32_t max_items_per_instance, int32_t order, wpm_item *items, int64_t cap,
                 int64_t *n_out, int64_t *items_per_instance);
+int build_pruned_queue(const wpm_blocks *blocks, const float *cost, const int32_t *group,
+                       int32_t num, int32_t cbits, int32_t lanes, int32_t min_items_per_instance,
+                       int32_t max_items_per_instance, int32_t order, wpm_item *items,
+                       int64_t cap, int64_t *n_out, int64_t *items_per_instance);
 
 int pack_bins(const wpm_item *items, int64_t n, const float *cost, int32_t bins,
               wpm_item *out_items, int64_t *out_offsets, double *max_load);

@@ -250,14 +250,19 @@ int slot_stride_for(int q) { return q <= 4 ? 4 : 8; }
 }  // namespace
 
 int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
-                  int32_t k, int32_t max_facets, uint64_t seed, uint32_t *table, int64_t cap_words,
-                  wpm_instance_info *info) {
+                  int32_t k, const wpm_blocks *blocks, int32_t max_facets, uint64_t seed,
+                  uint32_t *table, int64_t cap_words, wpm_instance_info *info) {
     if (!info) return WPM_EINVAL;
     std::memset(info, 0, sizeof(*info));
     int st = validate_facets(n, m, facets, M);
     if (st) return st;
     if (k < 0 || (k > 0 && !basis) || max_facets < 0) return WPM_EINVAL;
     if (k > WPM_MAX_K) return WPM_EKMAX;
+    if (blocks) {
+        st = validate_blocks(*blocks, k);
+        if (st) return st;
+        if (blocks->num_blocks == 0) blocks = nullptr;
+    }
     if (M > WPM_MAX_M) return WPM_ELIMIT;
     Incidence inc;
     inc.build(n, facets, M);
@@ -283,26 +288,63 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
     if (Q > WPM_MAX_SLOTS) return WPM_ELIMIT;
     const int QS = slot_stride_for(Q);
 
-    // Sample kernel vectors (all of them when 2^k is small), bit-sliced:
-    // X[t][s] bit b = coefficient t of sample 64 s + b.
+    // Sample the vectors the sweep visits (all of them when there are few),
+    // bit-sliced: X[t][s] bit b = coefficient t of sample 64 s + b.  A pruned
+    // instance visits only the product of its blocks' allowed sets times the
+    // free coordinates, so its samples come from that set.
     int T;
     bool exact = false;
-    if (k <= 13) {
-        T = 1 << k;
+    double visited = std::ldexp(1.0, k);
+    if (blocks) {
+        visited = std::ldexp(1.0, blocks->free_dims);
+        for (int b = 0; b < blocks->num_blocks; ++b) visited *= (double)blocks->count[b];
+    }
+    if (visited <= 8192.0) {
+        T = (int)visited;
         exact = true;
     } else {
         T = 8192;
     }
     const int TW = (T + 63) / 64;
     std::vector<uint64_t> X((size_t)std::max(k, 1) * TW, 0);
-    if (exact) {
-        for (int s = 0; s < T; ++s)
+    auto put = [&](int s, uint64_t x) {
+        for (uint64_t b = x; b; b &= b - 1)
+            X[(size_t)__builtin_ctzll(b) * TW + s / 64] |= 1ull << (s % 64);
+    };
+    SplitMix rng{seed ^ 0x5EEDF00DCAFEull};
+    if (!blocks) {
+        if (exact) {
+            for (int s = 0; s < T; ++s) put(s, (uint64_t)s);
+        } else {
             for (int t = 0; t < k; ++t)
-                if ((s >> t) & 1) X[(size_t)t * TW + s / 64] |= 1ull << (s % 64);
+                for (int s = 0; s < TW; ++s) X[(size_t)t * TW + s] = rng.next();
+        }
     } else {
-        SplitMix rng{seed ^ 0x5EEDF00DCAFEull};
-        for (int t = 0; t < k; ++t)
-            for (int s = 0; s < TW; ++s) X[(size_t)t * TW + s] = rng.next();
+        const int f = blocks->free_dims;
+        const uint64_t fmask = f >= 64 ? ~0ull : (1ull << f) - 1;
+        for (int s = 0; s < T; ++s) {
+            uint64_t x, idx = (uint64_t)s;
+            if (exact) {  // s in mixed radix: free part first, then block 0, 1, ...
+                x = idx & fmask;
+                idx >>= f;
+            } else {
+                x = rng.next() & fmask;
+            }
+            int sh = f;
+            for (int b = 0; b < blocks->num_blocks; ++b) {
+                const uint64_t cnt = blocks->count[b];
+                uint64_t d;
+                if (exact) {
+                    d = idx % cnt;
+                    idx /= cnt;
+                } else {
+                    d = rng.next() % cnt;
+                }
+                x |= (uint64_t)blocks->choice[b][d] << sh;
+                sh += blocks->size[b];
+            }
+            put(s, x);
+        }
     }
     const uint64_t tail_mask = (T % 64) ? ((1ull << (T % 64)) - 1) : ~0ull;
     // Parent bits of every critical ridge over the samples -> fail sets.

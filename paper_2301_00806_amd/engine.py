@@ -67,6 +67,38 @@ def kernel_basis(n: int, m: int, facets: np.ndarray) -> Tuple[np.ndarray, np.nda
     return ridges[:No.value].copy(), basis[:k * W].reshape(k, W) if W else basis[:0].reshape(0, 0), k
 
 
+# Free coordinates a pruned instance keeps by default.  One allowed block
+# tuple then spans at least 2^18 Gray indices: a full 256-lane workgroup with
+# 2^10 indices per lane.  Fewer free coordinates prune more but shorten the
+# lane chunks; on the 16384-instance learned batch 16, 18 and 20 gave kernel
+# times of 99.8, 93.3 and 104.0 ms.
+DEFAULT_MIN_FREE = 18
+
+
+def convenient_basis(n: int, m: int, facets: np.ndarray, basis: np.ndarray, k: int,
+                     min_free: int = DEFAULT_MIN_FREE):
+    """(convenient basis [k, W], wpm_blocks) of wpm_convenient_basis."""
+    F = np.ascontiguousarray(facets, dtype=np.uint32)
+    W = (len(F) + 31) // 32
+    Bf = np.ascontiguousarray(np.asarray(basis, dtype=np.uint32).reshape(-1))
+    if Bf.size == 0:
+        Bf = np.zeros(1, dtype=np.uint32)
+    out = np.zeros(max(1, k * W), dtype=np.uint32)
+    blk = L.Blocks()
+    st = L.lib().wpm_convenient_basis(n, m, _ptr(F), len(F), _ptr(Bf), k, min_free, _ptr(out),
+                                      ctypes.byref(blk))
+    L.check("wpm_convenient_basis", st)
+    return out[:k * W].reshape(k, W), blk
+
+
+def blocks_vectors(blk) -> int:
+    """Exact number of vectors a pruned sweep visits: 2^f * prod count[b]."""
+    v = 1 << int(blk.free_dims)
+    for b in range(int(blk.num_blocks)):
+        v *= int(blk.count[b])
+    return v
+
+
 @dataclass
 class Prepared:
     n: int
@@ -79,6 +111,7 @@ class Prepared:
     table: Optional[np.ndarray] = None
     info: Optional[L.InstanceInfo] = None
     tag: str = ""
+    blocks: Optional[L.Blocks] = None   # convenient-basis structure (pruned sweep)
 
     @property
     def W(self) -> int:
@@ -86,13 +119,22 @@ class Prepared:
 
     @property
     def vectors(self) -> int:
+        """Size of the kernel, 2^k."""
         return 1 << self.k
+
+    @property
+    def visited(self) -> int:
+        """Vectors the sweep visits: 2^k, or the pruned product."""
+        return self.vectors if self.blocks is None else blocks_vectors(self.blocks)
 
 
 def prepare(n: int, m: int, lam: Optional[Sequence[int]] = None,
             facets: Optional[Sequence[int]] = None, max_facets: Optional[int] = None,
-            seed: int = 0, pack: bool = True) -> Prepared:
-    """Candidates (if lambda is given), ridges, kernel basis and packed table."""
+            seed: int = 0, pack: bool = True, prune: bool = False,
+            min_free: int = DEFAULT_MIN_FREE) -> Prepared:
+    """Candidates (if lambda is given), ridges, kernel basis and packed table.
+    With `prune`, the basis is replaced by a convenient basis and the sweep
+    visits only the product of its blocks' allowed sets (same results)."""
     if facets is None:
         F = candidates(n, m, lam)
     else:
@@ -100,8 +142,11 @@ def prepare(n: int, m: int, lam: Optional[Sequence[int]] = None,
     if max_facets is None:
         max_facets = default_max_facets(n, m)
     ridges, B, k = kernel_basis(n, m, F)
+    blk = None
+    if prune and k > 0:
+        B, blk = convenient_basis(n, m, F, B, k, min_free)
     p = Prepared(n=n, m=m, facets=F, k=k, basis=np.ascontiguousarray(B), N=len(ridges),
-                 max_facets=max_facets)
+                 max_facets=max_facets, blocks=blk)
     if pack:
         pack_prepared(p, seed)
     return p
@@ -113,11 +158,12 @@ def pack_prepared(p: Prepared, seed: int = 0) -> None:
     Bf = np.ascontiguousarray(p.basis.reshape(-1), dtype=np.uint32)
     if Bf.size == 0:
         Bf = np.zeros(1, dtype=np.uint32)
-    st = lib.wpm_pack_instance(p.n, p.m, _ptr(p.facets), len(p.facets), _ptr(Bf), p.k,
+    bp = None if p.blocks is None else ctypes.byref(p.blocks)
+    st = lib.wpm_pack_instance(p.n, p.m, _ptr(p.facets), len(p.facets), _ptr(Bf), p.k, bp,
                                p.max_facets, seed, None, 0, ctypes.byref(info))
     L.check("wpm_pack_instance", st, (L.WPM_ECAP,))
     tab = np.zeros(info.table_words, dtype=np.uint32)
-    st = lib.wpm_pack_instance(p.n, p.m, _ptr(p.facets), len(p.facets), _ptr(Bf), p.k,
+    st = lib.wpm_pack_instance(p.n, p.m, _ptr(p.facets), len(p.facets), _ptr(Bf), p.k, bp,
                                p.max_facets, seed, _ptr(tab), info.table_words, ctypes.byref(info))
     L.check("wpm_pack_instance", st)
     p.table, p.info = tab, info
@@ -129,12 +175,14 @@ def kdim(inst) -> int:
     return kernel_basis(inst.n, inst.m, F)[2]
 
 
-def prepare_many(insts, seed: int = 0, threads: int = _POOL_THREADS) -> List[Prepared]:
+def prepare_many(insts, seed: int = 0, threads: int = _POOL_THREADS, prune: bool = False,
+                 min_free: int = DEFAULT_MIN_FREE) -> List[Prepared]:
     """prepare() over wpm_inputs.Instance objects, in parallel host threads
     (the C calls release the GIL)."""
     def one(a):
         i, inst = a
-        p = prepare(inst.n, inst.m, lam=inst.lam, facets=inst.facets, seed=seed + i)
+        p = prepare(inst.n, inst.m, lam=inst.lam, facets=inst.facets, seed=seed + i,
+                    prune=prune, min_free=min_free)
         p.tag = inst.tag
         return p
     with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
@@ -192,6 +240,16 @@ class DeviceBatch:
         self.tables = torch.from_numpy(host.view(np.int32)).to(device)
         self.offsets = torch.from_numpy(offs).to(device)
         self.k = np.array([p.k for p in self.preps], dtype=np.int32)
+        # wpm_blocks of every instance when any is pruned (plain ones: no blocks)
+        self.blocks = None
+        if any(p.blocks is not None for p in self.preps):
+            self.blocks = (L.Blocks * len(self.preps))()
+            for i, p in enumerate(self.preps):
+                if p.blocks is not None:
+                    self.blocks[i] = p.blocks
+                else:
+                    self.blocks[i].k = p.k
+                    self.blocks[i].free_dims = p.k
         self.cls = np.array([template_class(p.info) for p in self.preps], dtype=np.int64)
         self.c_batch = self._batch_of(self.preps)
         self.class_batches = {int(c): self._batch_of([p for p, q in zip(self.preps, self.cls) if q == c])
@@ -210,15 +268,23 @@ class DeviceBatch:
 
     @property
     def vectors(self) -> int:
+        """Sum of 2^k: the kernel vectors the batch covers."""
         return int(sum(1 << int(k) for k in self.k))
+
+    @property
+    def visited(self) -> int:
+        """Vectors a sweep of the batch visits (less than `vectors` when pruned)."""
+        return int(sum(p.visited for p in self.preps))
 
 
 def build_queue(k: np.ndarray, cbits: int, lanes: int, cost: Optional[np.ndarray] = None,
                 max_items_per_instance: int = 0, order: int = 0,
                 min_items_per_instance: int = 1, group: Optional[np.ndarray] = None,
-                return_counts: bool = False):
-    """Items of a batch (wpm_build_queue).  With `group`, items come out group
-    by group in decreasing group key; return_counts adds the items per instance."""
+                return_counts: bool = False, blocks=None):
+    """Items of a batch (wpm_build_queue; wpm_build_pruned_queue when
+    `blocks`, a ctypes array of wpm_blocks, is given).  With `group`, items
+    come out group by group in decreasing group key; return_counts adds the
+    items per instance."""
     lib = L.lib()
     ka = np.ascontiguousarray(k, dtype=np.int32)
     ca = None if cost is None else np.ascontiguousarray(cost, dtype=np.float32)
@@ -227,15 +293,20 @@ def build_queue(k: np.ndarray, cbits: int, lanes: int, cost: Optional[np.ndarray
     cp = None if ca is None else _ptr(ca, L.c_f32p)
     gp = None if ga is None else _ptr(ga, L.c_i32p)
     per = np.zeros(max(1, len(ka)), dtype=np.int64)
-    st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, gp, len(ka), cbits, lanes, min_items_per_instance,
-                             max_items_per_instance, order, None, 0, ctypes.byref(n), None)
-    L.check("wpm_build_queue", st, (L.WPM_ECAP, L.WPM_OK))
+    if blocks is not None:
+        if len(blocks) != len(ka):
+            raise ValueError("one wpm_blocks per instance")
+        call, name, first = lib.wpm_build_pruned_queue, "wpm_build_pruned_queue", blocks
+    else:
+        call, name, first = lib.wpm_build_queue, "wpm_build_queue", _ptr(ka, L.c_i32p)
+    st = call(first, cp, gp, len(ka), cbits, lanes, min_items_per_instance,
+              max_items_per_instance, order, None, 0, ctypes.byref(n), None)
+    L.check(name, st, (L.WPM_ECAP, L.WPM_OK))
     arr = np.zeros(max(1, n.value), dtype=ITEM_DTYPE)
-    st = lib.wpm_build_queue(_ptr(ka, L.c_i32p), cp, gp, len(ka), cbits, lanes, min_items_per_instance,
-                             max_items_per_instance, order,
-                             arr.ctypes.data_as(ctypes.POINTER(L.Item)), n.value, ctypes.byref(n),
-                             _ptr(per, L.c_i64p))
-    L.check("wpm_build_queue", st)
+    st = call(first, cp, gp, len(ka), cbits, lanes, min_items_per_instance,
+              max_items_per_instance, order, arr.ctypes.data_as(ctypes.POINTER(L.Item)), n.value,
+              ctypes.byref(n), _ptr(per, L.c_i64p))
+    L.check(name, st)
     arr = arr[:n.value]
     return (arr, per[:len(ka)]) if return_counts else arr
 
@@ -297,7 +368,7 @@ def class_items(batch: "DeviceBatch", cbits: int, lanes: int, cost: Optional[np.
     items, per = build_queue(batch.k, cbits, lanes, cost=cost, order=order,
                              min_items_per_instance=min_items_per_instance,
                              max_items_per_instance=max_items_per_instance,
-                             group=batch.cls, return_counts=True)
+                             group=batch.cls, return_counts=True, blocks=batch.blocks)
     segs, pos = [], 0
     for code in sorted(np.unique(batch.cls), reverse=True):
         n = int(per[batch.cls == code].sum())
@@ -472,7 +543,7 @@ def sweep(preps: Sequence[Prepared], mode: int = L.SCHED_DYNAMIC, cbits: int = 1
     sw = Sweeper(batch, cap=cap)
     items = build_queue(batch.k, cbits, wg_size, cost=cost,
                         max_items_per_instance=max_items_per_instance, order=order,
-                        min_items_per_instance=min_items_per_instance)
+                        min_items_per_instance=min_items_per_instance, blocks=batch.blocks)
     sw.set_items(items)
     sw.launch(mode, wg_size=wg_size, grid=grid)
     res = sw.result()

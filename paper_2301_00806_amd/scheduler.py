@@ -47,7 +47,7 @@ def _items(batch, split: bool, cbits: int, wg: int, cost=None, order: int = 0,
         return E.class_items(batch, cbits, wg, cost=cost, order=order,
                              min_items_per_instance=min_items)
     items = E.build_queue(batch.k, cbits, wg, cost=cost, order=order,
-                          min_items_per_instance=min_items)
+                          min_items_per_instance=min_items, blocks=batch.blocks)
     return items, [E.Segment(None, 0, len(items))]
 
 
@@ -86,7 +86,8 @@ def measure_labels(preps, cbits: int = 12, wg: int = 256, repeats: int = 2):
     _, clk, _ = E.device_query()
     batch = E.DeviceBatch(preps)
     sw = E.Sweeper(batch, cap=1 << 22)
-    items = E.build_queue(batch.k, cbits, wg, cost=np.ones(len(preps), np.float32), order=1)
+    items = E.build_queue(batch.k, cbits, wg, cost=np.ones(len(preps), np.float32), order=1,
+                          blocks=batch.blocks)
     sw.set_items(items, want_times=True)
     items = sw._items_host  # grouped by template class, as launched
     sw.launch(L.SCHED_DYNAMIC, wg_size=wg)

@@ -29,15 +29,16 @@ def shape_key(batch: "E.DeviceBatch") -> str:
     b = batch.c_batch
     gm = 2 if b.max_groups <= 2 else 4 if b.max_groups <= 4 else 8 if b.max_groups <= 8 else 16
     wm = 4 if b.max_words <= 4 else 16 if b.max_words <= 16 else 32
-    lv = int(np.log2(max(1.0, batch.vectors / max(1, len(batch.preps)))))
-    return f"{arch}/gm{gm}/qs{b.max_slots}/wm{wm}/v{lv}"
+    lv = int(np.log2(max(1.0, batch.visited / max(1, len(batch.preps)))))
+    pr = "/pruned" if batch.blocks is not None else ""
+    return f"{arch}/gm{gm}/qs{b.max_slots}/wm{wm}/v{lv}{pr}"
 
 
 def _sample(preps, budget_vectors: float):
-    order = sorted(range(len(preps)), key=lambda i: -preps[i].k)
+    order = sorted(range(len(preps)), key=lambda i: -preps[i].visited)
     chosen, tot = [], 0.0
     for i in order:
-        v = float(1 << preps[i].k)
+        v = float(preps[i].visited)
         if tot + v > budget_vectors and chosen:
             continue
         chosen.append(i)
@@ -66,11 +67,12 @@ def tune(preps: Sequence, cache: Optional[str] = DEFAULT_CACHE, budget_vectors: 
     sub = [preps[i] for i in idx]
     batch = E.DeviceBatch(sub)
     sw = E.Sweeper(batch, cap=1 << 24)
-    vec = batch.vectors
+    vec = batch.visited
     results, ref = [], None
     for wg in wgs:
         for cb in cbits:
-            items = E.build_queue(batch.k, cb, wg, cost=np.ones(len(sub), np.float32), order=1)
+            items = E.build_queue(batch.k, cb, wg, cost=np.ones(len(sub), np.float32), order=1,
+                                  blocks=batch.blocks)
             sw.set_items(items)
             sw.launch(L.SCHED_DYNAMIC, wg_size=wg)
             r = sw.result()

@@ -108,7 +108,8 @@ def test_capacity_overflow_keeps_counts_exact(E):
     sw.set_items(E.build_queue(batch.k, 7, 64))
     sw.launch(2, wg_size=64)
     res = sw.result()
-    assert res.total == full.total == 1302 and int(res.counts[0]) == 1302
+    want = O.count_wpm(3, [int(f) for f in p.facets], 0)
+    assert res.total == full.total == want and int(res.counts[0]) == want
     with pytest.raises(L.WpmError) as ei:
         sw.collect()
     assert ei.value.status == L.WPM_ECAP
