@@ -162,6 +162,56 @@ typedef struct wpm_blocks {
 int wpm_convenient_basis(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
                          int32_t k, int32_t min_free, uint32_t *basis_out, wpm_blocks *blocks);
 
+/* --------------------------------------------- facet conditions, properties */
+
+#define WPM_MAX_PROPS 8     /* affine properties per instance besides the facet bound */
+#define WPM_MAX_CLASSES 32  /* weight classes over all of an instance's properties */
+
+/*
+ * Forced-in and forced-out facets (Section 2.1's problem statement with facet
+ * conditions; Section 4.3 fixes the facets around a vertex this way): the
+ * complexes K in the span of `basis` with K_j = 1 for j in I and K_j = 0 for j
+ * in J form an affine coset K* + span(basis_out), found here by F2
+ * elimination on the rows I and J of the basis (the paper's column echelon
+ * form of B restricted to those rows).
+ *   facets[M], basis[k*W]    as from wpm_kernel_basis (any basis of ker A)
+ *   forced_in, forced_out    [W] facet bit masks (bit j = facet j), or NULL
+ *   basis_out[k*W]           receives k_out <= k vectors spanning the linear part
+ *   offset_out[W]            receives K*: the all-zero x of the coset (zero
+ *                            when I is empty: then the result is a subspace)
+ *   feasible                 receives 0 when no K satisfies the conditions
+ *                            (then k_out = 0), else 1
+ * Returns WPM_EINVAL if I and J share a facet or name bits >= M.
+ */
+int wpm_facet_conditions(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
+                         int32_t k, const uint32_t *forced_in, const uint32_t *forced_out,
+                         uint32_t *basis_out, int32_t *k_out, uint32_t *offset_out,
+                         int32_t *feasible);
+
+/*
+ * Optional parts of a packed instance.
+ *   offset        [W] offset K* of an affine coset (from wpm_facet_conditions),
+ *                 or NULL: the sweep then visits K = K* + sum x_t K_t for every
+ *                 x, including x = 0, whose complex is K* itself
+ *   num_props     affine properties g(K) = c0 + sum_c weight_c |K & mask_c|,
+ *                 kept when every g(K) > 0 (Section 2.1: the collection G;
+ *                 the facet bound max_facets is the property of Section 4.2
+ *                 and is passed on its own)
+ *   prop_c0       [num_props] constant terms
+ *   prop_classes  [num_props] weight classes of each property
+ *   class_weight  [sum of prop_classes] integer weights
+ *   class_mask    [sum of prop_classes][W] facet masks of the classes
+ * Sums are evaluated in 64-bit integers.
+ */
+typedef struct wpm_conditions {
+    const uint32_t *offset;
+    int32_t num_props;
+    const int32_t *prop_c0;
+    const int32_t *prop_classes;
+    const int32_t *class_weight;
+    const uint32_t *class_mask;
+} wpm_conditions;
+
 /* Summary of a packed instance. */
 typedef struct wpm_instance_info {
     int32_t n, m, M, N, k;
@@ -185,6 +235,8 @@ typedef struct wpm_instance_info {
  *   blocks                 NULL, or the structure of a convenient basis passed
  *                          as `basis`: the ridges are then ranked on vectors
  *                          drawn from the pruned set the sweep will visit
+ *   conds                  NULL, or an offset and affine properties (above);
+ *                          blocks and an offset cannot be combined (WPM_EINVAL)
  *   max_facets             bound on |K| (0 = none; the paper applies
  *                          wpm_ubt_bound(n) when m = n + 4, Algorithm 4.4)
  *   seed                   seeds the sampling that ranks ridges (any value;
@@ -195,8 +247,9 @@ typedef struct wpm_instance_info {
  * ridge's parent count exceeds the WPM_MAX_* limits.
  */
 int wpm_pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
-                      int32_t k, const wpm_blocks *blocks, int32_t max_facets, uint64_t seed,
-                      uint32_t *table, int64_t cap_words, wpm_instance_info *info);
+                      int32_t k, const wpm_blocks *blocks, const wpm_conditions *conds,
+                      int32_t max_facets, uint64_t seed, uint32_t *table, int64_t cap_words,
+                      wpm_instance_info *info);
 
 /* ------------------------------------------------------------ scheduling */
 
@@ -345,6 +398,7 @@ typedef struct wpm_host_instance {
     int32_t M, k;
     const uint32_t *facets; /* [M] */
     const uint32_t *basis;  /* [k * ceil(M/32)] */
+    const uint32_t *offset; /* [ceil(M/32)] offset K* of an affine coset, or NULL */
 } wpm_host_instance;
 
 /*

@@ -64,7 +64,17 @@ class Sched(ctypes.Structure):
 
 class HostInstance(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int32), ("k", ctypes.c_int32),
-                ("facets", ctypes.c_void_p), ("basis", ctypes.c_void_p)]
+                ("facets", ctypes.c_void_p), ("basis", ctypes.c_void_p),
+                ("offset", ctypes.c_void_p)]
+
+
+MAX_PROPS, MAX_CLASSES = 8, 32
+
+
+class Conditions(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_void_p), ("num_props", ctypes.c_int32),
+                ("prop_c0", ctypes.c_void_p), ("prop_classes", ctypes.c_void_p),
+                ("class_weight", ctypes.c_void_p), ("class_mask", ctypes.c_void_p)]
 
 
 _lib = None
@@ -108,9 +118,14 @@ def lib():
     L.wpm_ubt_bound.argtypes = [ctypes.c_int]
     L.wpm_pack_instance.restype = ctypes.c_int
     L.wpm_pack_instance.argtypes = [ctypes.c_int, ctypes.c_int, c_u32p, ctypes.c_int32, c_u32p,
-                                    ctypes.c_int32, ctypes.POINTER(Blocks), ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.POINTER(Blocks),
+                                    ctypes.POINTER(Conditions), ctypes.c_int32,
                                     ctypes.c_uint64, c_u32p, ctypes.c_int64,
                                     ctypes.POINTER(InstanceInfo)]
+    L.wpm_facet_conditions.restype = ctypes.c_int
+    L.wpm_facet_conditions.argtypes = [ctypes.c_int, ctypes.c_int, c_u32p, ctypes.c_int32, c_u32p,
+                                       ctypes.c_int32, c_u32p, c_u32p, c_u32p, c_i32p, c_u32p,
+                                       c_i32p]
     L.wpm_convenient_basis.restype = ctypes.c_int
     L.wpm_convenient_basis.argtypes = [ctypes.c_int, ctypes.c_int, c_u32p, ctypes.c_int32, c_u32p,
                                        ctypes.c_int32, ctypes.c_int32, c_u32p,
@@ -163,7 +178,7 @@ def check(call: str, status: int, ok=(WPM_OK,)) -> int:
 
 # Every symbol include/wpm.h declares.
 EXPORTED = ("wpm_strerror", "wpm_last_hip_error", "wpm_build_candidates", "wpm_kernel_basis",
-            "wpm_ubt_bound", "wpm_convenient_basis", "wpm_pack_instance", "wpm_build_queue",
+            "wpm_ubt_bound", "wpm_convenient_basis", "wpm_facet_conditions", "wpm_pack_instance", "wpm_build_queue",
             "wpm_build_pruned_queue", "wpm_pack_bins", "wpm_enumerate",
             "wpm_device_query", "wpm_persistent_grid", "wpm_valu_probe", "wpm_collect", "wpm_mlp_work_floats", "wpm_mlp_forward",
             "wpm_mlp_grad", "wpm_mlp_adam")

@@ -54,10 +54,19 @@ int wpm_convenient_basis(int n, int m, const uint32_t *facets, int32_t M, const 
     return wpm::convenient_basis(n, m, facets, M, basis, k, min_free, basis_out, blocks);
 }
 
+int wpm_facet_conditions(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
+                         int32_t k, const uint32_t *forced_in, const uint32_t *forced_out,
+                         uint32_t *basis_out, int32_t *k_out, uint32_t *offset_out,
+                         int32_t *feasible) {
+    return wpm::facet_conditions(n, m, facets, M, basis, k, forced_in, forced_out, basis_out,
+                                 k_out, offset_out, feasible);
+}
+
 int wpm_pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
-                      int32_t k, const wpm_blocks *blocks, int32_t max_facets, uint64_t seed,
-                      uint32_t *table, int64_t cap_words, wpm_instance_info *info) {
-    return wpm::pack_instance(n, m, facets, M, basis, k, blocks, max_facets, seed, table,
+                      int32_t k, const wpm_blocks *blocks, const wpm_conditions *conds,
+                      int32_t max_facets, uint64_t seed, uint32_t *table, int64_t cap_words,
+                      wpm_instance_info *info) {
+    return wpm::pack_instance(n, m, facets, M, basis, k, blocks, conds, max_facets, seed, table,
                               cap_words, info);
 }
 

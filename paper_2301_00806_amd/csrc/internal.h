@@ -14,6 +14,9 @@ namespace wpm {
 //   [4, 4 + (G-1) QS)      slot words of groups 1..G-1, QS words per group
 //                          (4-word groups stored as (a, a^b, c, c^d))
 //   [4 + (G-1) QS, +W)     the basis vector itself as facet words
+// then, for an affine coset, one more row in the same layout holding the
+// offset K*, and the property section: per property c0, class count, then per
+// class its weight and W mask words.
 constexpr uint32_t WPM_TABLE_MAGIC = 0x314D5057u;  // "WPM1"
 constexpr int WPM_HDR_WORDS = 16;
 enum {
@@ -28,7 +31,11 @@ enum {
     HDR_MAXF = 8,
     HDR_NCRIT = 9,
     HDR_NFILT = 10,
+    HDR_FLAGS = 11,   // bit 0: row kp holds the offset K* of an affine coset
+    HDR_PROPS = 12,   // word offset of the property section (0: none)
+    HDR_NPROPS = 13,  // affine properties besides the facet bound
 };
+constexpr uint32_t HDR_FLAG_OFFSET = 1;
 
 struct Incidence {
     int n = 0, M = 0, N = 0;
@@ -46,8 +53,12 @@ int build_candidates(int n, int m, const uint32_t *lambda, uint32_t *facets, int
 int kernel_basis(int n, int m, const uint32_t *facets, int32_t M, uint32_t *ridges_out,
                  int32_t cap_r, int32_t *N_out, uint32_t *basis, int32_t cap_k, int32_t *k_out);
 int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
-                  int32_t k, const wpm_blocks *blocks, int32_t max_facets, uint64_t seed,
-                  uint32_t *table, int64_t cap_words, wpm_instance_info *info);
+                  int32_t k, const wpm_blocks *blocks, const wpm_conditions *conds,
+                  int32_t max_facets, uint64_t seed, uint32_t *table, int64_t cap_words,
+                  wpm_instance_info *info);
+int facet_conditions(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
+                     int32_t k, const uint32_t *forced_in, const uint32_t *forced_out,
+                     uint32_t *basis_out, int32_t *k_out, uint32_t *offset_out, int32_t *feasible);
 int convenient_basis(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
                      int32_t k, int32_t min_free, uint32_t *basis_out, wpm_blocks *blocks);
 int validate_blocks(const wpm_blocks &b, int32_t k);

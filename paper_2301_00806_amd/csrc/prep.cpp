@@ -250,8 +250,9 @@ int slot_stride_for(int q) { return q <= 4 ? 4 : 8; }
 }  // namespace
 
 int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
-                  int32_t k, const wpm_blocks *blocks, int32_t max_facets, uint64_t seed,
-                  uint32_t *table, int64_t cap_words, wpm_instance_info *info) {
+                  int32_t k, const wpm_blocks *blocks, const wpm_conditions *conds,
+                  int32_t max_facets, uint64_t seed, uint32_t *table, int64_t cap_words,
+                  wpm_instance_info *info) {
     if (!info) return WPM_EINVAL;
     std::memset(info, 0, sizeof(*info));
     int st = validate_facets(n, m, facets, M);
@@ -263,16 +264,33 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
         if (st) return st;
         if (blocks->num_blocks == 0) blocks = nullptr;
     }
+    const uint32_t *offset = conds ? conds->offset : nullptr;
+    const int nprops = conds ? conds->num_props : 0;
+    int nclasses = 0;
+    if (nprops < 0 || nprops > WPM_MAX_PROPS) return WPM_EINVAL;
+    if (nprops > 0 && (!conds->prop_c0 || !conds->prop_classes || !conds->class_weight ||
+                       !conds->class_mask))
+        return WPM_EINVAL;
+    for (int q = 0; q < nprops; ++q) {
+        if (conds->prop_classes[q] < 0) return WPM_EINVAL;
+        nclasses += conds->prop_classes[q];
+    }
+    if (nclasses > WPM_MAX_CLASSES) return WPM_EINVAL;
+    if (offset && blocks) return WPM_EINVAL;  // block choices assume a linear span
     if (M > WPM_MAX_M) return WPM_ELIMIT;
     Incidence inc;
     inc.build(n, facets, M);
     const int W = (M + 31) / 32;
 
-    // Basis membership of each facet: frow[j] bit t = K_t contains facet j.
+    // Basis membership of each facet: frow[j] bit t = K_t contains facet j;
+    // offj[j] = the coset offset K* contains facet j.
     std::vector<uint64_t> frow(M, 0);
     for (int t = 0; t < k; ++t)
         for (int j = 0; j < M; ++j)
             if ((basis[(size_t)t * W + j / 32] >> (j % 32)) & 1u) frow[j] |= 1ull << t;
+    std::vector<char> offj(M, 0);
+    if (offset)
+        for (int j = 0; j < M; ++j) offj[j] = (char)((offset[j / 32] >> (j % 32)) & 1u);
 
     std::vector<int32_t> crit;
     int maxp = 0;
@@ -355,8 +373,9 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
         const int p0 = inc.parent_off[r], p = inc.parent_off[r + 1] - p0;
         for (int q = 0; q < p; ++q) {
             const uint64_t fr = frow[inc.parents[p0 + q]];
+            const uint64_t o = offj[inc.parents[p0 + q]] ? ~0ull : 0ull;
             for (int s = 0; s < TW; ++s) {
-                uint64_t acc = 0;
+                uint64_t acc = o;
                 for (uint64_t b = fr; b; b &= b - 1) acc ^= X[(size_t)__builtin_ctzll(b) * TW + s];
                 pw[(size_t)q * TW + s] = acc;
             }
@@ -421,7 +440,9 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
     if (G > WPM_MAX_GROUPS) return WPM_ELIMIT;
     const int kp = std::max(k, 7);
     const int RS = ((4 + (G - 1) * QS + W) + 3) & ~3;
-    const int64_t words = (int64_t)WPM_HDR_WORDS + (int64_t)kp * RS;
+    const int nrows = kp + (offset ? 1 : 0);  // the offset row follows the basis rows
+    const int64_t props_at = (int64_t)WPM_HDR_WORDS + (int64_t)nrows * RS;
+    const int64_t words = props_at + (nprops ? 2 * (int64_t)nprops + (int64_t)nclasses * (1 + W) : 0);
 
     info->n = n;
     info->m = m;
@@ -454,6 +475,9 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
     h[HDR_MAXF] = (uint32_t)max_facets;
     h[HDR_NCRIT] = (uint32_t)n_crit;
     h[HDR_NFILT] = (uint32_t)filt.size();
+    h[HDR_FLAGS] = offset ? HDR_FLAG_OFFSET : 0u;
+    h[HDR_PROPS] = nprops ? (uint32_t)props_at : 0u;
+    h[HDR_NPROPS] = (uint32_t)nprops;
     uint32_t *rows = table + WPM_HDR_WORDS;
     // slot word (group g, slot q) bit b  <-  parent q of the b-th ridge of group g
     auto place = [&](int c, int word_base, int bit, int slots_used) {
@@ -466,6 +490,7 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
                 const int t = __builtin_ctzll(b);
                 rows[(size_t)t * RS + word_base + q] |= 1u << bit;
             }
+            if (offj[inc.parents[p0 + q]]) rows[(size_t)kp * RS + word_base + q] |= 1u << bit;
         }
     };
     for (size_t b = 0; b < filt.size(); ++b) place(filt[b], 0, (int)b, 4);
@@ -477,11 +502,13 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
     // invertible linear change of coordinates, so Gray-code XOR updates still
     // apply, under which "at least 3 of a, b, c, d" takes two 3-input logic ops.
     auto transform4 = [&](int base) {
-        for (int t = 0; t < k; ++t) {
+        auto one = [&](int t) {
             uint32_t *r = rows + (size_t)t * RS + base;
             r[1] ^= r[0];
             r[3] ^= r[2];
-        }
+        };
+        for (int t = 0; t < k; ++t) one(t);
+        if (offset) one(kp);  // linear, so it applies to the offset as well
     };
     transform4(0);
     if (QS == 4)
@@ -489,6 +516,18 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
     const int koff = 4 + (G - 1) * QS;
     for (int t = 0; t < k; ++t)
         for (int w = 0; w < W; ++w) rows[(size_t)t * RS + koff + w] = basis[(size_t)t * W + w];
+    if (offset)
+        for (int w = 0; w < W; ++w) rows[(size_t)kp * RS + koff + w] = offset[w];
+    // property section: c0, class count, then (weight, W mask words) per class
+    uint32_t *pr = table + props_at;
+    for (int q = 0, cls = 0; q < nprops; ++q) {
+        *pr++ = (uint32_t)conds->prop_c0[q];
+        *pr++ = (uint32_t)conds->prop_classes[q];
+        for (int c = 0; c < conds->prop_classes[q]; ++c, ++cls) {
+            *pr++ = (uint32_t)conds->class_weight[cls];
+            for (int w = 0; w < W; ++w) *pr++ = conds->class_mask[(size_t)cls * W + w];
+        }
+    }
     return WPM_OK;
 }
 

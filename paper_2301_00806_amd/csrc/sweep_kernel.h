@@ -13,15 +13,18 @@
 // its first p-1 parent bits are set).  Work is split in two phases per block
 // of 64 steps:
 //   phase 1  the fast filter: 32 ridges in 4 slot words held in VGPRs,
-//            updated by 4 XORs and tested by 2 bit-logic ops per step; the
-//            steps where some lane passes are recorded in a 64-bit mask.
+//            updated by 4 XORs and tested by 2 bit-logic ops per step, the
+//            two halves of the block as interleaved chains; the steps where
+//            some lane passes are recorded in a 64-bit mask.
 //   phase 2  for each recorded step only: the lane's state is rebuilt as
 //            P ^ U[v], where P (per lane, VGPRs) is the contribution of the
 //            basis vectors above bit 6 and U (LDS, 64 rows staged per
 //            instance) the contribution of the low 6 bits v of x; the
 //            remaining ridge groups are checked with wave-uniform early exit,
 //            then the facet count |K| (the upper-bound property of Section
-//            4.2) and x != 0.  Survivors are compacted with a wave ballot and
+//            4.2), further affine properties g(K) > 0 (Section 2.1) and
+//            x != 0 (x = 0 is allowed when the instance is an affine coset
+//            K* + span, whose offset row is added to every state).  Survivors are compacted with a wave ballot and
 //            prefix count into per-wave chunks of record slots (one global
 //            atomic per chunk); per-instance counts are flushed once per item.
 // Dot products and parities reduce to AND, XOR and popcount on bit masks, as
@@ -37,8 +40,10 @@ namespace wpm {
 
 constexpr int DEV_HDR_WORDS = 16;  // must match the host packer's header size
 enum {
-    D_K = 1, D_KP = 2, D_M = 3, D_W = 4, D_G = 5, D_QS = 6, D_RS = 7, D_MAXF = 8
+    D_K = 1, D_KP = 2, D_M = 3, D_W = 4, D_G = 5, D_QS = 6, D_RS = 7, D_MAXF = 8,
+    D_FLAGS = 11, D_PROPS = 12, D_NPROPS = 13
 };
+constexpr uint32_t D_FLAG_OFFSET = 1;  // row kp holds the offset K* of an affine coset
 
 struct KArgs {
     int64_t num_items;
@@ -173,11 +178,12 @@ __global__ __launch_bounds__(512) void sweep_kernel(const uint32_t *__restrict__
         const int RS = (int)tab[D_RS];
         const int mqs = (QS == 4) ? 4 : (int)tab[D_QS];
         const uint32_t maxf = tab[D_MAXF];
+        const bool has_off = (tab[D_FLAGS] & D_FLAG_OFFSET) != 0u;
         const uint32_t *__restrict__ rows = tab + DEV_HDR_WORDS;
 
         uint32_t *lds_R = lds_U + WPM_TABLE_ROWS * RS;  // [kp][RS] basis rows
         if ((int64_t)inst != staged) {
-            for (int e = tid; e < kp * RS; e += blockDim.x) lds_R[e] = rows[e];
+            for (int e = tid; e < (kp + (has_off ? 1 : 0)) * RS; e += blockDim.x) lds_R[e] = rows[e];
             __syncthreads();
             // U[v] = XOR of rows t over the set bits t of v (v < 64)
             for (int e = tid; e < WPM_TABLE_ROWS * RS; e += blockDim.x) {
@@ -206,6 +212,8 @@ __global__ __launch_bounds__(512) void sweep_kernel(const uint32_t *__restrict__
                 const uint32_t msk = 0u - (uint32_t)((x0 >> t) & 1ull);
                 xor_row<GM, QS, WM>(P, lds_R + t * RS, msk, G, W, mqs);
             }
+            // an affine coset K* + span: every state carries the offset row
+            if (has_off) xor_row<GM, QS, WM>(P, lds_R + kp * RS, ~0u, G, W, mqs);
             uint32_t s0 = P[0], s1 = P[1], s2 = P[2], s3 = P[3];
             uint32_t d[6][4];
 #pragma unroll
@@ -216,28 +224,50 @@ __global__ __launch_bounds__(512) void sweep_kernel(const uint32_t *__restrict__
             const uint64_t nblk = 1ull << (c - 6);
             const int koff = 4 + (G - 1) * mqs;
             for (uint64_t blk = 0; blk < nblk; ++blk) {
-                // ---- phase 1: fast filter over 64 Gray steps.  The step mask
-                // is set on a rarely taken branch, so a step costs 7 VALU ops
-                // and one conditional branch.  (Testing pairs of steps with one
-                // branch was measured slower: every fired pair costs phase 2 a
-                // second step, and phase 2 is LDS-latency bound.)
+                // ---- phase 1: fast filter over 64 Gray steps, run as two
+                // interleaved chains: steps 0..31 from the block-start state
+                // and steps 32..63 from the state at step 32 (the low Gray
+                // bits of step 32 are bits 4 and 5).  Steps s and s + 32 flip
+                // the same basis vector, so both chains share the XOR operand;
+                // a step costs 7 VALU ops, and one rarely taken branch covers
+                // two steps.  The taken branch records each chain's step on
+                // its own, so phase 2 sees exactly the steps that passed.
                 uint64_t fire = 0;
+                uint32_t b0 = s0 ^ d[4][0] ^ d[5][0], b1 = s1 ^ d[4][1] ^ d[5][1];
+                uint32_t b2 = s2 ^ d[4][2] ^ d[5][2], b3 = s3 ^ d[4][3] ^ d[5][3];
 #pragma unroll
-                for (int s = 0; s < 64; ++s) {
-                    const uint32_t f = fail4(s0, s1, s2, s3);
+                for (int s = 0; s < 32; ++s) {
+                    const uint32_t fa = fail4(s0, s1, s2, s3);
+                    const uint32_t fb = fail4(b0, b1, b2, b3);
+                    const uint32_t fm = fa < fb ? fa : fb;
                     // inactive lanes may set a bit too; phase 2 masks them out
-                    if (__builtin_expect(__builtin_amdgcn_ballot_w64(f == 0u) != 0, 0)) {
-                        fire |= 1ull << s;
-                        asm volatile("" : "+s"(fire));
+                    if (__builtin_expect(__builtin_amdgcn_ballot_w64(fm == 0u) != 0, 0)) {
+                        if (__builtin_amdgcn_ballot_w64(fa == 0u)) fire |= 1ull << s;
+                        if (__builtin_amdgcn_ballot_w64(fb == 0u)) fire |= 1ull << (s + 32);
                     }
-                    if (s < 63) {
+                    if (s < 31) {
                         const int t = __builtin_ctz((unsigned)(s + 1));
                         s0 ^= d[t][0];
                         s1 ^= d[t][1];
                         s2 ^= d[t][2];
                         s3 ^= d[t][3];
+                        b0 ^= d[t][0];
+                        b1 ^= d[t][1];
+                        b2 ^= d[t][2];
+                        b3 ^= d[t][3];
+                        // opaque copies: keep each chain an in-place XOR
+                        // update (re-associating it from the block start
+                        // would hold extra base copies in VGPRs)
+                        asm volatile("" : "+v"(s0), "+v"(s1), "+v"(s2), "+v"(s3));
+                        asm volatile("" : "+v"(b0), "+v"(b1), "+v"(b2), "+v"(b3));
                     }
                 }
+                // the second chain ends at step 63: the state the block
+                // boundary continues from
+                s0 = b0;
+                s1 = b1;
+                s2 = b2;
+                s3 = b3;
                 // ---- phase 2: exact check of the recorded steps
                 while (fire) {
                     const int s = __builtin_ctzll(fire);
@@ -267,7 +297,8 @@ __global__ __launch_bounds__(512) void sweep_kernel(const uint32_t *__restrict__
                     }
                     const uint64_t i = i0 + (blk << 6) + (uint64_t)s;
                     const uint64_t x = i ^ (i >> 1);
-                    pass = pass && x != 0 && (k >= 64 || (x >> k) == 0);
+                    // x = 0 is the empty complex, except in a coset (K = K*)
+                    pass = pass && (x != 0 || has_off) && (k >= 64 || (x >> k) == 0);
                     if (__builtin_amdgcn_ballot_w64(pass)) {
                         int Wp = W, ko = koff;
                         asm volatile("" : "+s"(Wp), "+s"(ko));
@@ -275,7 +306,26 @@ __global__ __launch_bounds__(512) void sweep_kernel(const uint32_t *__restrict__
 #pragma unroll
                         for (int w = 0; w < WM; ++w)
                             if (w < Wp) cnt += __builtin_popcount(P[KR + w] ^ T[ko + w]);
-                        const bool ok = pass && (maxf == 0u || cnt <= maxf);
+                        bool ok = pass && (maxf == 0u || cnt <= maxf);
+                        // further affine properties g(K) = c0 + sum_c w_c |K & mask_c| > 0
+                        const uint32_t np = tab[D_NPROPS];
+                        if (np != 0u && __builtin_amdgcn_ballot_w64(ok) != 0) {
+                            const uint32_t *pr = tab + tab[D_PROPS];
+                            for (uint32_t q = 0; q < np; ++q) {
+                                int64_t g = (int32_t)pr[0];
+                                const uint32_t ncls = pr[1];
+                                pr += 2;
+                                for (uint32_t cl = 0; cl < ncls; ++cl) {
+                                    uint32_t sum = 0;
+#pragma unroll
+                                    for (int w = 0; w < WM; ++w)
+                                        if (w < Wp) sum += __builtin_popcount((P[KR + w] ^ T[ko + w]) & pr[1 + w]);
+                                    g += (int64_t)(int32_t)pr[0] * (int64_t)sum;
+                                    pr += 1 + Wp;
+                                }
+                                ok = ok && g > 0;
+                            }
+                        }
                         const uint64_t pball = __builtin_amdgcn_ballot_w64(pass);
                         const uint64_t bal = __builtin_amdgcn_ballot_w64(ok);
                         if (lane == 0) {

@@ -99,6 +99,39 @@ def blocks_vectors(blk) -> int:
     return v
 
 
+def facet_mask(facets: np.ndarray, chosen) -> np.ndarray:
+    """W-word bit mask (bit j = facet j) of the given facet vertex masks."""
+    F = np.asarray(facets, dtype=np.uint32)
+    pos = {int(f): j for j, f in enumerate(F)}
+    out = np.zeros(max(1, (len(F) + 31) // 32), dtype=np.uint32)
+    for f in chosen:
+        j = pos.get(int(f))
+        if j is None:
+            raise ValueError(f"facet {int(f):#x} is not a candidate")
+        out[j // 32] |= np.uint32(1 << (j % 32))
+    return out
+
+
+def facet_conditions(n: int, m: int, facets: np.ndarray, basis: np.ndarray, k: int,
+                     forced_in=(), forced_out=()):
+    """(basis [k', W], k', offset [W], feasible) of wpm_facet_conditions; the
+    forced facets are given as vertex masks."""
+    F = np.ascontiguousarray(facets, dtype=np.uint32)
+    W = (len(F) + 31) // 32
+    Bf = np.ascontiguousarray(np.asarray(basis, dtype=np.uint32).reshape(-1))
+    if Bf.size == 0:
+        Bf = np.zeros(1, dtype=np.uint32)
+    fi, fo = facet_mask(F, forced_in), facet_mask(F, forced_out)
+    out = np.zeros(max(1, k * W), dtype=np.uint32)
+    off = np.zeros(max(1, W), dtype=np.uint32)
+    ko, feas = ctypes.c_int32(0), ctypes.c_int32(0)
+    st = L.lib().wpm_facet_conditions(n, m, _ptr(F), len(F), _ptr(Bf), k, _ptr(fi), _ptr(fo),
+                                      _ptr(out), ctypes.byref(ko), _ptr(off), ctypes.byref(feas))
+    L.check("wpm_facet_conditions", st)
+    kk = ko.value
+    return out[:kk * W].reshape(kk, W), kk, off[:W].copy(), bool(feas.value)
+
+
 @dataclass
 class Prepared:
     n: int
@@ -112,6 +145,9 @@ class Prepared:
     info: Optional[L.InstanceInfo] = None
     tag: str = ""
     blocks: Optional[L.Blocks] = None   # convenient-basis structure (pruned sweep)
+    offset: Optional[np.ndarray] = None  # [W] offset K* of an affine coset
+    props: Optional[list] = None         # [(c0, [(weight, [facet masks])...])...]
+    feasible: bool = True                # False: the facet conditions admit no complex
 
     @property
     def W(self) -> int:
@@ -131,10 +167,14 @@ class Prepared:
 def prepare(n: int, m: int, lam: Optional[Sequence[int]] = None,
             facets: Optional[Sequence[int]] = None, max_facets: Optional[int] = None,
             seed: int = 0, pack: bool = True, prune: bool = False,
-            min_free: int = DEFAULT_MIN_FREE) -> Prepared:
+            min_free: int = DEFAULT_MIN_FREE, forced_in=None, forced_out=None,
+            properties=None) -> Prepared:
     """Candidates (if lambda is given), ridges, kernel basis and packed table.
     With `prune`, the basis is replaced by a convenient basis and the sweep
-    visits only the product of its blocks' allowed sets (same results)."""
+    visits only the product of its blocks' allowed sets (same results).
+    forced_in / forced_out (facet vertex masks) keep only complexes that
+    contain / avoid those facets; properties [(c0, [(weight, facets), ...])]
+    keep only complexes with c0 + sum weight * |K & facets| > 0 for each."""
     if facets is None:
         F = candidates(n, m, lam)
     else:
@@ -142,11 +182,21 @@ def prepare(n: int, m: int, lam: Optional[Sequence[int]] = None,
     if max_facets is None:
         max_facets = default_max_facets(n, m)
     ridges, B, k = kernel_basis(n, m, F)
-    blk = None
+    blk, off, feasible = None, None, True
+    if forced_in or forced_out:
+        B, k, off, feasible = facet_conditions(n, m, F, B, k, forced_in or (), forced_out or ())
+        if not forced_in or not feasible:
+            off = None          # a subspace (no offset), or nothing to sweep
+        if not feasible:
+            k = 0
+            B = B[:0]
     if prune and k > 0:
+        if off is not None:
+            raise ValueError("block pruning needs a linear span (no forced-in facets)")
         B, blk = convenient_basis(n, m, F, B, k, min_free)
     p = Prepared(n=n, m=m, facets=F, k=k, basis=np.ascontiguousarray(B), N=len(ridges),
-                 max_facets=max_facets, blocks=blk)
+                 max_facets=max_facets, blocks=blk, offset=off, props=properties,
+                 feasible=feasible)
     if pack:
         pack_prepared(p, seed)
     return p
@@ -159,14 +209,40 @@ def pack_prepared(p: Prepared, seed: int = 0) -> None:
     if Bf.size == 0:
         Bf = np.zeros(1, dtype=np.uint32)
     bp = None if p.blocks is None else ctypes.byref(p.blocks)
-    st = lib.wpm_pack_instance(p.n, p.m, _ptr(p.facets), len(p.facets), _ptr(Bf), p.k, bp,
+    conds, keep = _conditions(p)
+    cp = None if conds is None else ctypes.byref(conds)
+    st = lib.wpm_pack_instance(p.n, p.m, _ptr(p.facets), len(p.facets), _ptr(Bf), p.k, bp, cp,
                                p.max_facets, seed, None, 0, ctypes.byref(info))
     L.check("wpm_pack_instance", st, (L.WPM_ECAP,))
     tab = np.zeros(info.table_words, dtype=np.uint32)
-    st = lib.wpm_pack_instance(p.n, p.m, _ptr(p.facets), len(p.facets), _ptr(Bf), p.k, bp,
+    st = lib.wpm_pack_instance(p.n, p.m, _ptr(p.facets), len(p.facets), _ptr(Bf), p.k, bp, cp,
                                p.max_facets, seed, _ptr(tab), info.table_words, ctypes.byref(info))
     L.check("wpm_pack_instance", st)
     p.table, p.info = tab, info
+
+
+def _conditions(p: Prepared):
+    """wpm_conditions of a prepared instance (and the arrays it points into)."""
+    if p.offset is None and not p.props:
+        return None, None
+    keep = []
+    c = L.Conditions()
+    if p.offset is not None:
+        off = np.ascontiguousarray(p.offset, dtype=np.uint32)
+        keep.append(off)
+        c.offset = off.ctypes.data
+    props = p.props or []
+    c.num_props = len(props)
+    if props:
+        c0 = np.array([int(q[0]) for q in props], dtype=np.int32)
+        ncls = np.array([len(q[1]) for q in props], dtype=np.int32)
+        wts = np.array([int(w) for q in props for w, _ in q[1]] or [0], dtype=np.int32)
+        masks = np.concatenate([facet_mask(p.facets, fs) for q in props for _, fs in q[1]]
+                               or [np.zeros(1, np.uint32)])
+        keep += [c0, ncls, wts, masks]
+        c.prop_c0, c.prop_classes = c0.ctypes.data, ncls.ctypes.data
+        c.class_weight, c.class_mask = wts.ctypes.data, masks.ctypes.data
+    return c, keep
 
 
 def kdim(inst) -> int:
@@ -239,7 +315,11 @@ class DeviceBatch:
             host[o:o + len(p.table)] = p.table
         self.tables = torch.from_numpy(host.view(np.int32)).to(device)
         self.offsets = torch.from_numpy(offs).to(device)
-        self.k = np.array([p.k for p in self.preps], dtype=np.int32)
+        # kernel dimensions for the queue: a coset with k = 0 still holds one
+        # complex (x = 0 is K*), so it is queued as k = 1; the table's own k
+        # keeps the sweep to x = 0
+        self.k = np.array([p.k if (p.k > 0 or p.offset is None) else 1 for p in self.preps],
+                          dtype=np.int32)
         # wpm_blocks of every instance when any is pruned (plain ones: no blocks)
         self.blocks = None
         if any(p.blocks is not None for p in self.preps):
@@ -504,8 +584,13 @@ class Sweeper:
             if Bf.size == 0:
                 Bf = np.zeros(1, np.uint32)
             keep.append(Bf)
+            off = None
+            if p.offset is not None:
+                off = np.ascontiguousarray(p.offset, dtype=np.uint32)
+                keep.append(off)
             hosts[i] = L.HostInstance(M=len(p.facets), k=p.k, facets=p.facets.ctypes.data,
-                                      basis=Bf.ctypes.data)
+                                      basis=Bf.ctypes.data,
+                                      offset=None if off is None else off.ctypes.data)
         h_counts = np.zeros(max(1, len(preps)), dtype=np.uint64)
         offs = np.zeros(len(preps) + 1, dtype=np.int64)
         words = ctypes.c_int64(0)

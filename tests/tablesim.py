@@ -14,7 +14,33 @@ HDR = 16
 
 def header(tab):
     h = [int(v) for v in tab[:HDR]]
-    return dict(k=h[1], kp=h[2], M=h[3], W=h[4], G=h[5], QS=h[6], RS=h[7], maxf=h[8])
+    return dict(k=h[1], kp=h[2], M=h[3], W=h[4], G=h[5], QS=h[6], RS=h[7], maxf=h[8],
+                offset=bool(h[11] & 1), props_at=h[12], nprops=h[13])
+
+
+def offset_row(tab):
+    """The coset offset K* in row layout (zeros for a linear span)."""
+    h = header(tab)
+    if not h["offset"]:
+        return np.zeros(h["RS"], dtype=np.uint64)
+    at = HDR + h["kp"] * h["RS"]
+    return tab[at:at + h["RS"]].astype(np.uint64)
+
+
+def properties(tab):
+    """[(c0, [(weight, mask words)...])...] from the property section."""
+    h = header(tab)
+    out, at = [], h["props_at"]
+    for _ in range(h["nprops"]):
+        c0 = int(np.int32(np.uint32(tab[at])))
+        ncls = int(tab[at + 1])
+        at += 2
+        cls = []
+        for _ in range(ncls):
+            cls.append((int(np.int32(np.uint32(tab[at]))), [int(v) for v in tab[at + 1:at + 1 + h["W"]]]))
+            at += 1 + h["W"]
+        out.append((c0, cls))
+    return out
 
 
 def rows(tab):
@@ -58,13 +84,24 @@ def accept(h, v):
             return False
     koff = 4 + (h["G"] - 1) * h["QS"]
     cnt = sum(bin(int(v[koff + w])).count("1") for w in range(h["W"]))
-    return h["maxf"] == 0 or cnt <= h["maxf"]
+    if not (h["maxf"] == 0 or cnt <= h["maxf"]):
+        return False
+    for c0, cls in h.get("props", []):
+        g = c0
+        for wgt, mask in cls:
+            g += wgt * sum(bin(int(v[koff + w]) & mask[w]).count("1") for w in range(h["W"]))
+        if g <= 0:
+            return False
+    return True
 
 
 def survivors_direct(tab):
     h = header(tab)
+    h["props"] = properties(tab)
     R = rows(tab)
-    return sorted(x for x in range(1, 1 << h["k"]) if accept(h, state(R, x)))
+    off = offset_row(tab)
+    first = 0 if h["offset"] else 1    # x = 0 is K* in a coset, else the empty complex
+    return sorted(x for x in range(first, 1 << h["k"]) if accept(h, state(R, x) ^ off))
 
 
 def survivors_walk(tab, cbits=7):
@@ -107,9 +144,9 @@ def survivors_walk(tab, cbits=7):
     return sorted(out)
 
 
-def facets_of_x(basis, facets, x):
-    W = basis.shape[1] if basis.ndim == 2 else 0
-    K = np.zeros(W, dtype=np.uint32)
+def facets_of_x(basis, facets, x, offset=None):
+    W = basis.shape[1] if basis.ndim == 2 and basis.shape[0] else (len(facets) + 31) // 32
+    K = np.zeros(W, dtype=np.uint32) if offset is None else np.array(offset, dtype=np.uint32)
     t = 0
     while x:
         if x & 1:

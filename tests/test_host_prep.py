@@ -94,10 +94,10 @@ def test_pack_rejects_large_k_and_bad_input():
     info = L.InstanceInfo()
     F = np.array([0b011, 0b101, 0b110], dtype=np.uint32)
     B = np.zeros(70 * 1, dtype=np.uint32)
-    st = lib.wpm_pack_instance(2, 3, E._ptr(F), 3, E._ptr(B), 70, None, 0, 0, None, 0, ctypes.byref(info))
+    st = lib.wpm_pack_instance(2, 3, E._ptr(F), 3, E._ptr(B), 70, None, None, 0, 0, None, 0, ctypes.byref(info))
     assert st == L.WPM_EKMAX
     bad = np.array([0b011, 0b011], dtype=np.uint32)  # duplicate facet
-    st = lib.wpm_pack_instance(2, 3, E._ptr(bad), 2, E._ptr(B), 0, None, 0, 0, None, 0, ctypes.byref(info))
+    st = lib.wpm_pack_instance(2, 3, E._ptr(bad), 2, E._ptr(B), 0, None, None, 0, 0, None, 0, ctypes.byref(info))
     assert st == L.WPM_EINVAL
     wrong = np.array([0b111], dtype=np.uint32)  # size 3, n = 2
     No, ko = ctypes.c_int32(), ctypes.c_int32()
