@@ -212,6 +212,28 @@ typedef struct wpm_conditions {
     const uint32_t *class_mask;
 } wpm_conditions;
 
+/* ------------------------------------------------------------ IDCM orbits */
+
+/*
+ * One characteristic matrix per IDCM orbit of Lambda(n, p) (Section 4.2: the
+ * (n+p) x p matrices [M; I_p] over F2 with no repeated rows, under S_n x S_p;
+ * the proposition on IDCM orbits there makes the binary matroids of one orbit
+ * isomorphic, so the enumeration of Algorithm 4.4 needs one representative
+ * each).  The rows of
+ * M are distinct vectors of weight >= 2 (a dual characteristic map is nonzero
+ * and injective), so an orbit is an n-subset of them up to coordinate
+ * permutations; the representative is the orbit's least subset in
+ * lexicographic order of the increasing row lists, and orbits come in that
+ * order.
+ *   n, p       1 <= n <= 26, 2 <= p <= 5 (the paper's case is p = 4)
+ *   lam_out    [cap * (n+p)] host array: representative r is the matrix
+ *              [I_n | M] as n+p columns (bit t = row t), the lambda argument
+ *              of wpm_build_candidates with m = n + p
+ *   count      receives the number of orbits; WPM_ECAP if it exceeds cap
+ *              (lam_out may be NULL to count only)
+ */
+int wpm_idcm_orbits(int n, int p, uint32_t *lam_out, int64_t cap, int64_t *count);
+
 /* Summary of a packed instance. */
 typedef struct wpm_instance_info {
     int32_t n, m, M, N, k;

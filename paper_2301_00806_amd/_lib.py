@@ -122,6 +122,8 @@ def lib():
                                     ctypes.POINTER(Conditions), ctypes.c_int32,
                                     ctypes.c_uint64, c_u32p, ctypes.c_int64,
                                     ctypes.POINTER(InstanceInfo)]
+    L.wpm_idcm_orbits.restype = ctypes.c_int
+    L.wpm_idcm_orbits.argtypes = [ctypes.c_int, ctypes.c_int, c_u32p, ctypes.c_int64, c_i64p]
     L.wpm_facet_conditions.restype = ctypes.c_int
     L.wpm_facet_conditions.argtypes = [ctypes.c_int, ctypes.c_int, c_u32p, ctypes.c_int32, c_u32p,
                                        ctypes.c_int32, c_u32p, c_u32p, c_u32p, c_i32p, c_u32p,
@@ -178,7 +180,7 @@ def check(call: str, status: int, ok=(WPM_OK,)) -> int:
 
 # Every symbol include/wpm.h declares.
 EXPORTED = ("wpm_strerror", "wpm_last_hip_error", "wpm_build_candidates", "wpm_kernel_basis",
-            "wpm_ubt_bound", "wpm_convenient_basis", "wpm_facet_conditions", "wpm_pack_instance", "wpm_build_queue",
+            "wpm_ubt_bound", "wpm_convenient_basis", "wpm_facet_conditions", "wpm_idcm_orbits", "wpm_pack_instance", "wpm_build_queue",
             "wpm_build_pruned_queue", "wpm_pack_bins", "wpm_enumerate",
             "wpm_device_query", "wpm_persistent_grid", "wpm_valu_probe", "wpm_collect", "wpm_mlp_work_floats", "wpm_mlp_forward",
             "wpm_mlp_grad", "wpm_mlp_adam")

@@ -54,6 +54,10 @@ int wpm_convenient_basis(int n, int m, const uint32_t *facets, int32_t M, const 
     return wpm::convenient_basis(n, m, facets, M, basis, k, min_free, basis_out, blocks);
 }
 
+int wpm_idcm_orbits(int n, int p, uint32_t *lam_out, int64_t cap, int64_t *count) {
+    return wpm::idcm_orbits(n, p, lam_out, cap, count);
+}
+
 int wpm_facet_conditions(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
                          int32_t k, const uint32_t *forced_in, const uint32_t *forced_out,
                          uint32_t *basis_out, int32_t *k_out, uint32_t *offset_out,

@@ -62,6 +62,7 @@ int facet_conditions(int n, int m, const uint32_t *facets, int32_t M, const uint
 int convenient_basis(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
                      int32_t k, int32_t min_free, uint32_t *basis_out, wpm_blocks *blocks);
 int validate_blocks(const wpm_blocks &b, int32_t k);
+int idcm_orbits(int n, int p, uint32_t *lam_out, int64_t cap, int64_t *count);
 void cost_features(const wpm_instance_info &info, const Incidence &inc,
                    const std::vector<int32_t> &crit, float *out);
 int build_queue(const int32_t *k, const float *cost, const int32_t *group, int32_t num,

@@ -99,6 +99,18 @@ def blocks_vectors(blk) -> int:
     return v
 
 
+def idcm_orbits(n: int, p: int = 4) -> List[List[int]]:
+    """One characteristic matrix [I_n | M] (as n + p columns) per IDCM orbit
+    of Lambda(n, p) (wpm_idcm_orbits)."""
+    lib = L.lib()
+    cnt = ctypes.c_int64(0)
+    L.check("wpm_idcm_orbits", lib.wpm_idcm_orbits(n, p, None, 0, ctypes.byref(cnt)))
+    m = n + p
+    out = np.zeros(max(1, cnt.value * m), dtype=np.uint32)
+    L.check("wpm_idcm_orbits", lib.wpm_idcm_orbits(n, p, _ptr(out), cnt.value, ctypes.byref(cnt)))
+    return [[int(v) for v in out[r * m:(r + 1) * m]] for r in range(cnt.value)]
+
+
 def facet_mask(facets: np.ndarray, chosen) -> np.ndarray:
     """W-word bit mask (bit j = facet j) of the given facet vertex masks."""
     F = np.asarray(facets, dtype=np.uint32)
