@@ -234,6 +234,40 @@ typedef struct wpm_conditions {
  */
 int wpm_idcm_orbits(int n, int p, uint32_t *lam_out, int64_t cap, int64_t *count);
 
+/* ------------------------------------------------------ complexes (filters) */
+
+#define WPM_CX_FULL_PICARD 1 /* K uses all m vertices: Pic(K) = m - n */
+#define WPM_CX_SEED 2        /* K satisfies the seedness condition */
+
+/*
+ * Filters of Algorithm 4.4 on enumerated complexes.  A list of complexes is
+ * offsets[num + 1] (offsets[0] = 0) into facets[]: complex i has the facet
+ * vertex masks facets[offsets[i] .. offsets[i+1]), all below 2^m, m <= 16.
+ *
+ * wpm_complex_filters sets flags[i]:
+ *   WPM_CX_FULL_PICARD  the complex uses every vertex of [m], so its Picard
+ *                       number (vertices minus n) is m - n (Algorithm 4.4
+ *                       discards complexes with Pic(K) < 4 at m = n + 4)
+ *   WPM_CX_SEED         the seedness condition (Section 3, seedness from
+ *                       minimal non-faces): no edge {v, w} of K such that every
+ *                       minimal non-face contains both v and w or neither
+ */
+int wpm_complex_filters(int n, int m, int64_t num, const int64_t *offsets,
+                        const uint32_t *facets, uint8_t *flags);
+
+/*
+ * Isomorphism classes of a list of complexes (Section 3, checking isomorphism
+ * with minimal non-faces): vertices are coloured by the increasing sizes of
+ * the minimal non-faces containing them, and two complexes are isomorphic iff
+ * a colour-preserving relabelling maps one set of minimal non-faces onto the
+ * other (the search assigns vertices class by class and backtracks on the
+ * first non-face that does not map).  class_of[i] receives the class of
+ * complex i, classes numbered 0, 1, ... in order of first appearance;
+ * *num_classes receives their number.
+ */
+int wpm_iso_classes(int m, int64_t num, const int64_t *offsets, const uint32_t *facets,
+                    int64_t *class_of, int64_t *num_classes);
+
 /* Summary of a packed instance. */
 typedef struct wpm_instance_info {
     int32_t n, m, M, N, k;

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libwpm.so")
 WPM_OK, WPM_EINVAL, WPM_ECAP, WPM_EKMAX, WPM_EHIP, WPM_ELIMIT = 0, -1, -2, -3, -4, -5
 SCHED_PLAIN, SCHED_STATIC, SCHED_DYNAMIC, SCHED_PACKED = 0, 1, 2, 3
 FLAG_ACCUMULATE = 1
+CX_FULL_PICARD, CX_SEED = 1, 2
 MAX_K = 64
 
 c_u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -122,6 +123,11 @@ def lib():
                                     ctypes.POINTER(Conditions), ctypes.c_int32,
                                     ctypes.c_uint64, c_u32p, ctypes.c_int64,
                                     ctypes.POINTER(InstanceInfo)]
+    L.wpm_complex_filters.restype = ctypes.c_int
+    L.wpm_complex_filters.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, c_i64p, c_u32p,
+                                      ctypes.POINTER(ctypes.c_uint8)]
+    L.wpm_iso_classes.restype = ctypes.c_int
+    L.wpm_iso_classes.argtypes = [ctypes.c_int, ctypes.c_int64, c_i64p, c_u32p, c_i64p, c_i64p]
     L.wpm_idcm_orbits.restype = ctypes.c_int
     L.wpm_idcm_orbits.argtypes = [ctypes.c_int, ctypes.c_int, c_u32p, ctypes.c_int64, c_i64p]
     L.wpm_facet_conditions.restype = ctypes.c_int
@@ -180,7 +186,8 @@ def check(call: str, status: int, ok=(WPM_OK,)) -> int:
 
 # Every symbol include/wpm.h declares.
 EXPORTED = ("wpm_strerror", "wpm_last_hip_error", "wpm_build_candidates", "wpm_kernel_basis",
-            "wpm_ubt_bound", "wpm_convenient_basis", "wpm_facet_conditions", "wpm_idcm_orbits", "wpm_pack_instance", "wpm_build_queue",
+            "wpm_ubt_bound", "wpm_convenient_basis", "wpm_facet_conditions", "wpm_idcm_orbits",
+            "wpm_complex_filters", "wpm_iso_classes", "wpm_pack_instance", "wpm_build_queue",
             "wpm_build_pruned_queue", "wpm_pack_bins", "wpm_enumerate",
             "wpm_device_query", "wpm_persistent_grid", "wpm_valu_probe", "wpm_collect", "wpm_mlp_work_floats", "wpm_mlp_forward",
             "wpm_mlp_grad", "wpm_mlp_adam")

@@ -20,7 +20,7 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-SOURCES = ["prep.cpp", "prune.cpp", "conditions.cpp", "orbits.cpp", "sched.cpp", "capi.cpp", "engine.hip", "mlp.hip", "probe.hip",
+SOURCES = ["prep.cpp", "prune.cpp", "conditions.cpp", "orbits.cpp", "complexes.cpp", "sched.cpp", "capi.cpp", "engine.hip", "mlp.hip", "probe.hip",
            "sweep_g2.hip", "sweep_g4.hip", "sweep_g8.hip", "sweep_g16.hip"]
 
 

@@ -58,6 +58,16 @@ int wpm_idcm_orbits(int n, int p, uint32_t *lam_out, int64_t cap, int64_t *count
     return wpm::idcm_orbits(n, p, lam_out, cap, count);
 }
 
+int wpm_complex_filters(int n, int m, int64_t num, const int64_t *offsets,
+                        const uint32_t *facets, uint8_t *flags) {
+    return wpm::complex_filters(n, m, num, offsets, facets, flags);
+}
+
+int wpm_iso_classes(int m, int64_t num, const int64_t *offsets, const uint32_t *facets,
+                    int64_t *class_of, int64_t *num_classes) {
+    return wpm::iso_classes(m, num, offsets, facets, class_of, num_classes);
+}
+
 int wpm_facet_conditions(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
                          int32_t k, const uint32_t *forced_in, const uint32_t *forced_out,
                          uint32_t *basis_out, int32_t *k_out, uint32_t *offset_out,

@@ -63,6 +63,10 @@ int convenient_basis(int n, int m, const uint32_t *facets, int32_t M, const uint
                      int32_t k, int32_t min_free, uint32_t *basis_out, wpm_blocks *blocks);
 int validate_blocks(const wpm_blocks &b, int32_t k);
 int idcm_orbits(int n, int p, uint32_t *lam_out, int64_t cap, int64_t *count);
+int complex_filters(int n, int m, int64_t num, const int64_t *offsets, const uint32_t *facets,
+                    uint8_t *flags);
+int iso_classes(int m, int64_t num, const int64_t *offsets, const uint32_t *facets,
+                int64_t *class_of, int64_t *num_classes);
 void cost_features(const wpm_instance_info &info, const Incidence &inc,
                    const std::vector<int32_t> &crit, float *out);
 int build_queue(const int32_t *k, const float *cost, const int32_t *group, int32_t num,

@@ -1,0 +1,133 @@
+"""Algorithm 4.4 up to its isomorphism step, on the engine.
+
+For Picard number 4 and dimension n - 1 (m = n + 4):
+  1. one characteristic matrix per IDCM orbit (wpm_idcm_orbits);
+  2. for each, every weak pseudo-manifold with facets in F(lambda) and at
+     most f(n) facets (the GPU sweep; the upper-bound property of Section
+     4.2) -- the union is the set K(n, 4) of the algorithm's line 7;
+  3. discard complexes with Pic(K) < 4 or failing the seedness condition
+     (wpm_complex_filters) -- line 13;
+  4. one representative per isomorphism class (wpm_iso_classes) -- line 15.
+The PL-sphere test of the algorithm's last step is not part of this engine.
+Counts at lines 7 and 13 count labelled complexes, so they depend on which
+representative each orbit gets; line 15 does not.
+"""
+from __future__ import annotations
+
+import ctypes
+import time
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib as L
+from . import engine as E
+
+Complex = Tuple[int, ...]
+
+
+def _pack(complexes: Sequence[Sequence[int]]):
+    offs = np.zeros(len(complexes) + 1, dtype=np.int64)
+    if complexes:
+        offs[1:] = np.cumsum([len(K) for K in complexes])
+    fac = np.zeros(max(1, int(offs[-1])), dtype=np.uint32)
+    pos = 0
+    for K in complexes:
+        fac[pos:pos + len(K)] = K
+        pos += len(K)
+    return offs, fac
+
+
+def complex_filters(n: int, m: int, complexes: Sequence[Sequence[int]]) -> np.ndarray:
+    """Flags per complex: CX_FULL_PICARD, CX_SEED (wpm_complex_filters)."""
+    offs, fac = _pack(complexes)
+    flags = np.zeros(max(1, len(complexes)), dtype=np.uint8)
+    L.check("wpm_complex_filters", L.lib().wpm_complex_filters(
+        n, m, len(complexes), E._ptr(offs, L.c_i64p), E._ptr(fac),
+        flags.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return flags[:len(complexes)]
+
+
+def iso_classes(m: int, complexes: Sequence[Sequence[int]]):
+    """(class of each complex, number of classes) (wpm_iso_classes)."""
+    offs, fac = _pack(complexes)
+    cls = np.zeros(max(1, len(complexes)), dtype=np.int64)
+    num = ctypes.c_int64(0)
+    L.check("wpm_iso_classes", L.lib().wpm_iso_classes(
+        m, len(complexes), E._ptr(offs, L.c_i64p), E._ptr(fac), E._ptr(cls, L.c_i64p),
+        ctypes.byref(num)))
+    return cls[:len(complexes)], int(num.value)
+
+
+@dataclass
+class SeedReport:
+    n: int
+    orbits: int
+    max_k: int
+    line7: int                 # |K(n,4)|: union of the sweeps' outputs
+    line13: int                # after the Picard-number and seedness filters
+    line15: int                # isomorphism classes
+    representatives: List[Complex] = field(default_factory=list)
+    seconds: dict = field(default_factory=dict)
+
+
+def gpu_enumerator(cbits: int = 12, wg: int = 256, prune: bool = False, cap: int = 1 << 24):
+    """Enumerator over a list of prepared orbit instances on the GPU sweep."""
+    def run(preps):
+        _, sets = E.sweep(preps, cbits=cbits, wg_size=wg, cap=cap)
+        return sets
+    run.prune = prune
+    return run
+
+
+def colorable_seeds_pic4(n: int, enumerate_sets: Optional[Callable] = None,
+                         prune: bool = False) -> SeedReport:
+    """Algorithm 4.4 for Picard number 4 up to its isomorphism step.
+    `enumerate_sets(preps) -> per-instance result lists` defaults to the GPU
+    sweep; any exact enumerator of weak pseudo-manifolds may stand in."""
+    m = n + 4
+    t = {}
+    t0 = time.perf_counter()
+    lams = E.idcm_orbits(n)
+    preps = [E.prepare(n, m, lam=lam, prune=prune and getattr(enumerate_sets, "prune", True))
+             for lam in lams]
+    t["prepare"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    run = enumerate_sets or gpu_enumerator(prune=prune)
+    sets = run(preps)
+    t["enumerate"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    union = sorted({tuple(sorted(K)) for s in sets for K in s})
+    flags = complex_filters(n, m, union)
+    want = L.CX_FULL_PICARD | L.CX_SEED
+    kept = [K for K, f in zip(union, flags) if (int(f) & want) == want]
+    cls, num = iso_classes(m, kept)
+    reps = [None] * num
+    for K, c in zip(kept, cls):
+        if reps[c] is None:
+            reps[c] = K
+    t["filters"] = time.perf_counter() - t0
+    return SeedReport(n=n, orbits=len(lams), max_k=max(p.k for p in preps), line7=len(union),
+                      line13=len(kept), line15=num, representatives=reps, seconds=t)
+
+
+def main(argv=None) -> None:
+    """Run the pipeline for the given dimensions and print one JSON line each."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="Algorithm 4.4 (Picard number 4) up to the "
+                                             "isomorphism step, on the GPU sweep")
+    ap.add_argument("n", type=int, nargs="+")
+    ap.add_argument("--prune", action="store_true", help="sweep convenient bases")
+    args = ap.parse_args(argv)
+    for n in args.n:
+        rep = colorable_seeds_pic4(n, prune=args.prune)
+        print(json.dumps({"n": n, "orbits": rep.orbits, "max_k": rep.max_k, "line7": rep.line7,
+                          "line13": rep.line13, "line15": rep.line15,
+                          "seconds": {k: round(v, 2) for k, v in rep.seconds.items()}}),
+              flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,45 @@
+"""Algorithm 4.4 up to its isomorphism step with the GPU sweep: Table 2's
+line 15 (isomorphism classes of seeds of Picard number 4 supporting an IDCM)
+for n = 2..7, and, for n <= 5, the same labelled sets at lines 7 and 13 as the
+pipeline run on the oracle's enumeration."""
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+import oracle as O
+from test_seeds import TABLE2_LINE15
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_00806_amd import engine, seeds
+    engine.device_query()
+    return seeds
+
+
+def oracle_enumerator(preps):
+    with ThreadPoolExecutor(16) as ex:
+        return list(ex.map(lambda p: O.enumerate_wpm(p.n, [int(f) for f in p.facets],
+                                                     p.max_facets), preps))
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 7])
+def test_table2_line15_on_gpu(S, n):
+    print(f"[gpu] Algorithm 4.4 for n={n}", flush=True)
+    rep = S.colorable_seeds_pic4(n)
+    print(f"[gpu] n={n}: line7 {rep.line7} line13 {rep.line13} line15 {rep.line15} "
+          f"{rep.seconds}", flush=True)
+    assert rep.line15 == TABLE2_LINE15[n]
+    if n <= 5:
+        ref = S.colorable_seeds_pic4(n, enumerate_sets=oracle_enumerator)
+        assert (rep.line7, rep.line13) == (ref.line7, ref.line13)
+        assert rep.representatives == ref.representatives
+    # the pruned sweep reaches the same classes
+    if n in (4, 6):
+        assert S.colorable_seeds_pic4(n, prune=True).line15 == TABLE2_LINE15[n]
