@@ -96,6 +96,22 @@ struct Layout {
 
 // P ^= row & msk over the words an instance uses.  Registers use the
 // template stride QS; the row uses the instance's own stride mqs (<= QS).
+// P = row over the words an instance uses (unused register words are 0).
+template <int GM, int QS, int WM>
+__device__ __forceinline__ void load_row(uint32_t *P, const uint32_t *row, int G, int W, int mqs) {
+    constexpr int KR = Layout<GM, QS, WM>::KR;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) P[q] = row[q];
+#pragma unroll
+    for (int g = 1; g < GM; ++g)
+#pragma unroll
+        for (int q = 0; q < QS; ++q)
+            P[4 + (g - 1) * QS + q] = (g < G && (QS == 4 || q < mqs)) ? row[4 + (g - 1) * mqs + q] : 0u;
+    const int koff = 4 + (G - 1) * mqs;
+#pragma unroll
+    for (int w = 0; w < WM; ++w) P[KR + w] = w < W ? row[koff + w] : 0u;
+}
+
 template <int GM, int QS, int WM>
 __device__ __forceinline__ void xor_row(uint32_t *P, const uint32_t *row, uint32_t msk, int G,
                                         int W, int mqs) {
@@ -197,6 +213,19 @@ __global__ __launch_bounds__(512) void sweep_kernel(const uint32_t *__restrict__
             __syncthreads();
             staged = inst;
         }
+        // State at the start of the item's first chunk (x of Gray index
+        // first * 2^c, plus the coset offset), one word per lane; every lane
+        // then adds only the rows where its own start differs from it.
+        uint32_t *lds_P = lds_R + (kp + 1) * RS;
+        const uint64_t iref = first << c;
+        const uint64_t xref = iref ^ (iref >> 1);
+        for (int w = tid; w < RS; w += blockDim.x) {
+            uint32_t acc = has_off ? lds_R[kp * RS + w] : 0u;
+            for (int t = 6; t < kp; ++t)
+                if ((xref >> t) & 1ull) acc ^= lds_R[t * RS + w];
+            lds_P[w] = acc;
+        }
+        __syncthreads();
 
         uint32_t item_cnt = 0;  // results of this item found by this wave
         // wave-uniform test (readfirstlane tells the compiler so)
@@ -206,14 +235,16 @@ __global__ __launch_bounds__(512) void sweep_kernel(const uint32_t *__restrict__
             const uint64_t i0 = active ? (j << c) : 0;
             const uint64_t x0 = i0 ^ (i0 >> 1);
             uint32_t P[PW];
-#pragma unroll
-            for (int q = 0; q < PW; ++q) P[q] = 0;
+            load_row<GM, QS, WM>(P, lds_P, G, W, mqs);
+            // rows where this lane's start differs from the reference start
+            // (consecutive chunks: usually only the few rows above c - 1);
+            // rows no lane of the wave needs are skipped as a whole
+            const uint64_t dx = active ? (x0 ^ xref) : 0ull;
             for (int t = 6; t < kp; ++t) {
-                const uint32_t msk = 0u - (uint32_t)((x0 >> t) & 1ull);
-                xor_row<GM, QS, WM>(P, lds_R + t * RS, msk, G, W, mqs);
+                const bool bit = ((dx >> t) & 1ull) != 0;
+                if (__builtin_amdgcn_ballot_w64(bit) == 0) continue;
+                xor_row<GM, QS, WM>(P, lds_R + t * RS, bit ? ~0u : 0u, G, W, mqs);
             }
-            // an affine coset K* + span: every state carries the offset row
-            if (has_off) xor_row<GM, QS, WM>(P, lds_R + kp * RS, ~0u, G, W, mqs);
             uint32_t s0 = P[0], s1 = P[1], s2 = P[2], s3 = P[3];
             uint32_t d[6][4];
 #pragma unroll
@@ -269,6 +300,7 @@ __global__ __launch_bounds__(512) void sweep_kernel(const uint32_t *__restrict__
                 s2 = b2;
                 s3 = b3;
                 // ---- phase 2: exact check of the recorded steps
+                fire = rfl64(fire);  // wave-uniform: keep it in scalar registers
                 while (fire) {
                     const int s = __builtin_ctzll(fire);
                     fire &= fire - 1;

@@ -72,11 +72,23 @@ class SeedReport:
     seconds: dict = field(default_factory=dict)
 
 
-def gpu_enumerator(cbits: int = 12, wg: int = 256, prune: bool = False, cap: int = 1 << 24):
-    """Enumerator over a list of prepared orbit instances on the GPU sweep."""
+def gpu_enumerator(cbits: int = 12, wg: int = 256, prune: bool = False, cap: int = 1 << 24,
+                   per_instance: bool = False, log: Optional[Callable[[str], None]] = None):
+    """Enumerator over a list of prepared orbit instances on the GPU sweep:
+    one batched sweep, or one sweep per instance (with a log line each)."""
     def run(preps):
-        _, sets = E.sweep(preps, cbits=cbits, wg_size=wg, cap=cap)
-        return sets
+        if not per_instance:
+            _, sets = E.sweep(preps, cbits=cbits, wg_size=wg, cap=cap)
+            return sets
+        out = []
+        for i, p in enumerate(preps):
+            t0 = time.perf_counter()
+            res, sets = E.sweep([p], cbits=cbits, wg_size=wg, cap=cap)
+            out.append(sets[0])
+            if log:
+                log(f"orbit {i + 1}/{len(preps)}: k={p.k}, {p.visited:.3e} vectors, "
+                    f"{int(res.total)} complexes, {time.perf_counter() - t0:.1f}s")
+        return out
     run.prune = prune
     return run
 
@@ -121,8 +133,11 @@ def main(argv=None) -> None:
     ap.add_argument("n", type=int, nargs="+")
     ap.add_argument("--prune", action="store_true", help="sweep convenient bases")
     args = ap.parse_args(argv)
+    import sys
+    log = lambda msg: print(f"[seeds] {msg}", file=sys.stderr, flush=True)
     for n in args.n:
-        rep = colorable_seeds_pic4(n, prune=args.prune)
+        run = gpu_enumerator(prune=args.prune, per_instance=True, log=log)
+        rep = colorable_seeds_pic4(n, enumerate_sets=run, prune=args.prune)
         print(json.dumps({"n": n, "orbits": rep.orbits, "max_k": rep.max_k, "line7": rep.line7,
                           "line13": rep.line13, "line15": rep.line15,
                           "seconds": {k: round(v, 2) for k, v in rep.seconds.items()}}),
