@@ -523,10 +523,11 @@ class Sweeper:
                        if want_times else None)
 
     def launch(self, mode: int, wg_size: int = 256, grid: int = 0, stream=None,
-               seg_events: bool = False) -> None:
+               seg_events: bool = False, accumulate: bool = False) -> None:
         """One wpm_enumerate call per segment, in order, on `stream`.  With
         seg_events, HIP events bracket each segment's launch on that stream
-        (self.seg_events: list of (class, start event, end event))."""
+        (self.seg_events: list of (class, start event, end event)).  With
+        accumulate, counts and records add to those of earlier launches."""
         torch = self.torch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -541,7 +542,8 @@ class Sweeper:
             cb = self.batch.c_batch if sg.cls is None else self.batch.class_batches[sg.cls]
             n = sg.end - sg.start
             bins = self._seg_bins[i] if self._segments else None
-            s = L.Sched(mode=mode, wg_size=wg_size, grid=grid, flags=L.FLAG_ACCUMULATE if i else 0,
+            s = L.Sched(mode=mode, wg_size=wg_size, grid=grid,
+                        flags=L.FLAG_ACCUMULATE if (i or accumulate) else 0,
                         d_items=self._items_dev.data_ptr() + 16 * sg.start,
                         h_items=items.ctypes.data + 16 * sg.start if n else None,
                         num_items=n, d_scratch=self.scratch.data_ptr(),

@@ -72,8 +72,57 @@ class SeedReport:
     seconds: dict = field(default_factory=dict)
 
 
+def sliced_sweep(p, cbits: int = 12, wg: int = 256, cap: int = 1 << 24,
+                 max_items: int = 1 << 22, log: Optional[Callable[[str], None]] = None):
+    """Sweep one (pruned) instance in slices of at most about max_items items:
+    each slice fixes the choices of the highest blocks, so its queue is the
+    product of the remaining blocks' choices (the table is the same for every
+    slice).  Counts and records accumulate on the device.  Returns the result
+    list of the instance."""
+    import itertools
+    batch = E.DeviceBatch([p])
+    sw = E.Sweeper(batch, cap=cap)
+    cls = int(batch.cls[0])
+    blk = p.blocks
+    nb = 0 if blk is None else int(blk.num_blocks)
+    # fix the top blocks until the rest yields at most max_items items
+    per_tuple = 1
+    if blk is not None and nb:
+        c = min(cbits, max(7, int(blk.free_dims) - 8))
+        per_tuple = max(1, (1 << (int(blk.free_dims) - c)) // wg)
+    fixed = 0
+    rest = 1 if blk is None else int(np.prod([int(blk.count[b]) for b in range(nb)], dtype=np.float64))
+    while fixed < nb and rest * per_tuple > max_items:
+        rest //= int(blk.count[nb - 1 - fixed])
+        fixed += 1
+    top = list(range(nb - fixed, nb))
+    combos = list(itertools.product(*[range(int(blk.count[b])) for b in top])) if fixed else [()]
+    t0 = time.perf_counter()
+    for si, digits in enumerate(combos):
+        if blk is not None:
+            part = L.Blocks()
+            ctypes.pointer(part)[0] = blk
+            for b, d in zip(top, digits):
+                part.choice[b][0] = blk.choice[b][d]
+                part.count[b] = 1
+            items = E.build_queue(np.array([p.k], np.int32), cbits, wg, blocks=(L.Blocks * 1)(part))
+        else:
+            items = E.build_queue(np.array([p.k], np.int32), cbits, wg)
+        sw.set_items(items, segments=[E.Segment(cls, 0, len(items))])
+        sw.launch(L.SCHED_DYNAMIC, wg_size=wg, accumulate=si > 0)
+        if log and (si % max(1, len(combos) // 20) == 0 or si == len(combos) - 1):
+            sw.torch.cuda.synchronize()
+            log(f"slice {si + 1}/{len(combos)} ({len(items)} items), "
+                f"{time.perf_counter() - t0:.1f}s")
+    res = sw.result()
+    if res.slots > cap:
+        raise L.WpmError("sliced sweep (survivor buffer overflow)", L.WPM_ECAP)
+    return sw.collect()[0]
+
+
 def gpu_enumerator(cbits: int = 12, wg: int = 256, prune: bool = False, cap: int = 1 << 24,
-                   per_instance: bool = False, log: Optional[Callable[[str], None]] = None):
+                   per_instance: bool = False, log: Optional[Callable[[str], None]] = None,
+                   sliced: bool = False):
     """Enumerator over a list of prepared orbit instances on the GPU sweep:
     one batched sweep, or one sweep per instance (with a log line each)."""
     def run(preps):
@@ -83,18 +132,22 @@ def gpu_enumerator(cbits: int = 12, wg: int = 256, prune: bool = False, cap: int
         out = []
         for i, p in enumerate(preps):
             t0 = time.perf_counter()
-            res, sets = E.sweep([p], cbits=cbits, wg_size=wg, cap=cap)
-            out.append(sets[0])
+            if sliced:
+                out.append(sliced_sweep(p, cbits=cbits, wg=wg, cap=cap, log=log))
+            else:
+                _, sets = E.sweep([p], cbits=cbits, wg_size=wg, cap=cap)
+                out.append(sets[0])
             if log:
                 log(f"orbit {i + 1}/{len(preps)}: k={p.k}, {p.visited:.3e} vectors, "
-                    f"{int(res.total)} complexes, {time.perf_counter() - t0:.1f}s")
+                    f"{len(out[-1])} complexes, {time.perf_counter() - t0:.1f}s")
         return out
     run.prune = prune
     return run
 
 
 def colorable_seeds_pic4(n: int, enumerate_sets: Optional[Callable] = None,
-                         prune: bool = False) -> SeedReport:
+                         prune: bool = False, min_free: int = E.DEFAULT_MIN_FREE,
+                         max_orbits: int = 0) -> SeedReport:
     """Algorithm 4.4 for Picard number 4 up to its isomorphism step.
     `enumerate_sets(preps) -> per-instance result lists` defaults to the GPU
     sweep; any exact enumerator of weak pseudo-manifolds may stand in."""
@@ -102,8 +155,10 @@ def colorable_seeds_pic4(n: int, enumerate_sets: Optional[Callable] = None,
     t = {}
     t0 = time.perf_counter()
     lams = E.idcm_orbits(n)
-    preps = [E.prepare(n, m, lam=lam, prune=prune and getattr(enumerate_sets, "prune", True))
-             for lam in lams]
+    if max_orbits:
+        lams = lams[:max_orbits]
+    preps = [E.prepare(n, m, lam=lam, prune=prune and getattr(enumerate_sets, "prune", True),
+                       min_free=min_free) for lam in lams]
     t["prepare"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     run = enumerate_sets or gpu_enumerator(prune=prune)
@@ -132,12 +187,19 @@ def main(argv=None) -> None:
                                              "isomorphism step, on the GPU sweep")
     ap.add_argument("n", type=int, nargs="+")
     ap.add_argument("--prune", action="store_true", help="sweep convenient bases")
+    ap.add_argument("--min-free", type=int, default=0,
+                    help="free coordinates of a pruned instance (0 = engine default)")
+    ap.add_argument("--sliced", action="store_true",
+                    help="sweep each orbit in slices over its highest blocks (large n)")
+    ap.add_argument("--orbits", type=int, default=0, help="only the first N orbits (timing)")
     args = ap.parse_args(argv)
     import sys
     log = lambda msg: print(f"[seeds] {msg}", file=sys.stderr, flush=True)
     for n in args.n:
-        run = gpu_enumerator(prune=args.prune, per_instance=True, log=log)
-        rep = colorable_seeds_pic4(n, enumerate_sets=run, prune=args.prune)
+        run = gpu_enumerator(prune=args.prune, per_instance=True, log=log, sliced=args.sliced)
+        rep = colorable_seeds_pic4(n, enumerate_sets=run, prune=args.prune,
+                                   min_free=args.min_free or E.DEFAULT_MIN_FREE,
+                                   max_orbits=args.orbits)
         print(json.dumps({"n": n, "orbits": rep.orbits, "max_k": rep.max_k, "line7": rep.line7,
                           "line13": rep.line13, "line15": rep.line15,
                           "seconds": {k: round(v, 2) for k, v in rep.seconds.items()}}),
