@@ -202,6 +202,19 @@ int wpm_facet_conditions(int n, int m, const uint32_t *facets, int32_t M, const 
  *   class_weight  [sum of prop_classes] integer weights
  *   class_mask    [sum of prop_classes][W] facet masks of the classes
  * Sums are evaluated in 64-bit integers.
+ *   max_groups    0, or at most this many 32-ridge groups (1..WPM_MAX_GROUPS)
+ *                 kept resident in the sweep; see "deferred ridges" below
+ *
+ * Deferred ridges.  The sweep holds at most WPM_MAX_GROUPS groups of 32
+ * critical ridges (the most rejecting ones, in the packer's greedy order),
+ * each with at most WPM_MAX_SLOTS + 1 parents.  Any further critical ridges
+ * (and ridges with more parents) are deferred: the table lists their parents,
+ * and wpm_enumerate follows the sweep with a verification pass that checks
+ * them on every survivor record, retires the records that fail (instance
+ * ~0) and takes them off the counts.  Results and counts stay exact, except
+ * after a record-buffer overflow: records that were not stored cannot be
+ * verified, so the counts of instances with deferred ridges are then upper
+ * bounds.
  */
 typedef struct wpm_conditions {
     const uint32_t *offset;
@@ -210,6 +223,7 @@ typedef struct wpm_conditions {
     const int32_t *prop_classes;
     const int32_t *class_weight;
     const uint32_t *class_mask;
+    int32_t max_groups;
 } wpm_conditions;
 
 /* ------------------------------------------------------------ IDCM orbits */
@@ -278,6 +292,7 @@ typedef struct wpm_instance_info {
     int32_t n_filter;     /* ridges in the fast filter group */
     int32_t row_words;    /* words per basis row of the packed table */
     int32_t max_facets;   /* upper bound applied (0 = none) */
+    int32_t n_deferred;   /* critical ridges checked by the verification pass */
     int64_t table_words;  /* size of the packed table in uint32 words */
     double filter_pass;   /* estimated fraction of x passing the filter */
     double full_pass;     /* estimated fraction of x passing every ridge */
@@ -299,8 +314,8 @@ typedef struct wpm_instance_info {
  *                          never changes results)
  *   table, cap_words       host output; with table == NULL or a too small
  *                          cap the call returns WPM_ECAP after filling info
- * Returns WPM_EKMAX if k > 64, WPM_ELIMIT if M, the critical ridge count or a
- * ridge's parent count exceeds the WPM_MAX_* limits.
+ * Returns WPM_EKMAX if k > 64, WPM_ELIMIT if M exceeds WPM_MAX_M (critical
+ * ridges beyond the resident groups are deferred, see above).
  */
 int wpm_pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_t *basis,
                       int32_t k, const wpm_blocks *blocks, const wpm_conditions *conds,
@@ -393,7 +408,11 @@ typedef struct wpm_batch {
     int32_t max_kp;            /* max over the batch of max(k, 7) (LDS sizing) */
     const uint32_t *d_tables;  /* device: packed tables, concatenated (16-byte aligned each) */
     const int64_t *d_offsets;  /* device: word offset of each table in d_tables */
+    int32_t flags;             /* WPM_BATCH_DEFERRED: some table has deferred ridges */
+    int32_t reserved;
 } wpm_batch;
+
+#define WPM_BATCH_DEFERRED 1 /* run the verification pass of deferred ridges */
 
 #define WPM_FLAG_ACCUMULATE 1 /* do not clear d_counts, d_total, d_stats: add to them */
 

@@ -11,6 +11,7 @@ WPM_OK, WPM_EINVAL, WPM_ECAP, WPM_EKMAX, WPM_EHIP, WPM_ELIMIT = 0, -1, -2, -3, -
 SCHED_PLAIN, SCHED_STATIC, SCHED_DYNAMIC, SCHED_PACKED = 0, 1, 2, 3
 FLAG_ACCUMULATE = 1
 CX_FULL_PICARD, CX_SEED = 1, 2
+BATCH_DEFERRED = 1
 MAX_K = 64
 
 c_u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -35,7 +36,7 @@ class Blocks(ctypes.Structure):
 class InstanceInfo(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
                 ("n", "m", "M", "N", "k", "W", "n_crit", "groups", "slots", "n_filter",
-                 "row_words", "max_facets")] + [
+                 "row_words", "max_facets", "n_deferred")] + [
         ("table_words", ctypes.c_int64),
         ("filter_pass", ctypes.c_double),
         ("full_pass", ctypes.c_double),
@@ -52,7 +53,8 @@ class Batch(ctypes.Structure):
     _fields_ = [("num_instances", ctypes.c_int32), ("max_row_words", ctypes.c_int32),
                 ("max_groups", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("max_words", ctypes.c_int32), ("max_kp", ctypes.c_int32),
-                ("d_tables", ctypes.c_void_p), ("d_offsets", ctypes.c_void_p)]
+                ("d_tables", ctypes.c_void_p), ("d_offsets", ctypes.c_void_p),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Sched(ctypes.Structure):
@@ -75,7 +77,8 @@ MAX_PROPS, MAX_CLASSES = 8, 32
 class Conditions(ctypes.Structure):
     _fields_ = [("offset", ctypes.c_void_p), ("num_props", ctypes.c_int32),
                 ("prop_c0", ctypes.c_void_p), ("prop_classes", ctypes.c_void_p),
-                ("class_weight", ctypes.c_void_p), ("class_mask", ctypes.c_void_p)]
+                ("class_weight", ctypes.c_void_p), ("class_mask", ctypes.c_void_p),
+                ("max_groups", ctypes.c_int32)]
 
 
 _lib = None

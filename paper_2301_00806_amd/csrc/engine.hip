@@ -19,6 +19,56 @@ __global__ void zero_u64(unsigned long long *p, int64_t n) {
     if (i < n) p[i] = 0ull;
 }
 
+// Verification pass for deferred ridges: every survivor record of an
+// instance whose table lists deferred ridges has its facet vector K rebuilt
+// from the table rows; if some deferred ridge has more than 2 parents in K,
+// the record is retired (instance ~0) and taken off the counts.
+__global__ void verify_deferred(const uint32_t *__restrict__ tables,
+                                const int64_t *__restrict__ offsets, int32_t num_instances,
+                                uint64_t *surv, uint64_t cap, const unsigned long long *slots,
+                                unsigned long long *counts, unsigned long long *total) {
+    const uint64_t n = *slots < cap ? *slots : cap;
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t inst = surv[2 * r + 1];
+        if (inst >= (uint64_t)num_instances) continue;  // unused slot or retired record
+        const uint32_t *tab = tables + offsets[inst];
+        const uint32_t nd = tab[HDR_NDEFER];
+        if (nd == 0u) continue;
+        const uint64_t x = surv[2 * r];
+        const int kp = (int)tab[HDR_KP], W = (int)tab[HDR_W], G = (int)tab[HDR_G];
+        const int QS = (int)tab[HDR_QS], RS = (int)tab[HDR_RS];
+        const int koff = 4 + (G - 1) * QS;
+        const uint32_t *rows = tab + WPM_HDR_WORDS;
+        uint32_t K[32];
+        for (int w = 0; w < 32; ++w)
+            K[w] = (w < W && (tab[HDR_FLAGS] & HDR_FLAG_OFFSET)) ? rows[(size_t)kp * RS + koff + w] : 0u;
+        for (uint64_t b = x; b; b &= b - 1) {
+            const int t = __builtin_ctzll(b);
+            if (t >= kp) break;
+            for (int w = 0; w < W; ++w) K[w] ^= rows[(size_t)t * RS + koff + w];
+        }
+        const uint32_t *d = tab + tab[HDR_DEFER];
+        bool ok = true;
+        for (uint32_t q = 0; q < nd && ok; ++q) {
+            const uint32_t p = d[0];
+            uint32_t cnt = 0;
+            for (uint32_t j = 0; j < p; ++j) {
+                const uint32_t f = d[1 + j];
+                cnt += (K[(f >> 5) & 31u] >> (f & 31u)) & 1u;
+            }
+            ok = cnt <= 2u;
+            d += 1 + p;
+        }
+        if (!ok) {
+            atomicAdd(counts + inst, ~0ull);  // minus one
+            atomicAdd(total, ~0ull);
+            surv[2 * r] = 0;
+            surv[2 * r + 1] = ~0ull;
+        }
+    }
+}
+
 int hip_fail(const char *what, hipError_t e) {
     set_hip_error(what, (int)e, hipGetErrorString(e));
     return WPM_EHIP;
@@ -104,6 +154,19 @@ int persistent_grid(const wpm_batch *b, int wg_size, int32_t *grid) {
     return WPM_OK;
 }
 
+// The verification pass of deferred ridges, when the batch has any.
+int verify(const wpm_batch *b, uint64_t *d_surv, uint64_t cap, uint64_t *d_counts,
+           uint64_t *d_total, hipStream_t st) {
+    if (!(b->flags & WPM_BATCH_DEFERRED) || cap == 0) return WPM_OK;
+    const uint64_t nb = std::min<uint64_t>((cap + 255) / 256, 16384);
+    hipLaunchKernelGGL(verify_deferred, dim3((unsigned)nb), dim3(256), 0, st, b->d_tables,
+                       b->d_offsets, b->num_instances, d_surv, cap,
+                       (const unsigned long long *)(d_total + 1), (unsigned long long *)d_counts,
+                       (unsigned long long *)d_total);
+    HIP_TRY(hipGetLastError());
+    return WPM_OK;
+}
+
 int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t cap,
               uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats, void *stream) {
     if (!b || !s || !d_counts || !d_total || (cap > 0 && !d_surv)) return WPM_EINVAL;
@@ -168,14 +231,14 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
                            s->d_items, a));
             i = e;
         }
-        return WPM_OK;
+        return verify(b, d_surv, cap, d_counts, d_total, st);
     }
     int32_t grid = s->grid;
     if (grid <= 0 && (rc = persistent_grid(b, s->wg_size, &grid))) return rc;
     a.mode = (s->mode == WPM_SCHED_STATIC) ? 1 : (s->mode == WPM_SCHED_DYNAMIC) ? 2 : 3;
     HIP_TRY(launch(gm, qs, wm, dim3((unsigned)grid), block, lds, st, b->d_tables, b->d_offsets,
                    s->d_items, a));
-    return WPM_OK;
+    return verify(b, d_surv, cap, d_counts, d_total, st);
 }
 
 int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv, uint64_t cap,

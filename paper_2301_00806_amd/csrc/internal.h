@@ -15,8 +15,9 @@ namespace wpm {
 //                          (4-word groups stored as (a, a^b, c, c^d))
 //   [4 + (G-1) QS, +W)     the basis vector itself as facet words
 // then, for an affine coset, one more row in the same layout holding the
-// offset K*, and the property section: per property c0, class count, then per
-// class its weight and W mask words.
+// offset K*, the property section (per property c0, class count, then per
+// class its weight and W mask words) and the deferred-ridge section (per
+// ridge its parent count, then the parents' facet indices).
 constexpr uint32_t WPM_TABLE_MAGIC = 0x314D5057u;  // "WPM1"
 constexpr int WPM_HDR_WORDS = 16;
 enum {
@@ -34,6 +35,8 @@ enum {
     HDR_FLAGS = 11,   // bit 0: row kp holds the offset K* of an affine coset
     HDR_PROPS = 12,   // word offset of the property section (0: none)
     HDR_NPROPS = 13,  // affine properties besides the facet bound
+    HDR_DEFER = 14,   // word offset of the deferred-ridge section (0: none)
+    HDR_NDEFER = 15,  // deferred ridges: checked on survivors by the verification pass
 };
 constexpr uint32_t HDR_FLAG_OFFSET = 1;
 

@@ -276,6 +276,8 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
         nclasses += conds->prop_classes[q];
     }
     if (nclasses > WPM_MAX_CLASSES) return WPM_EINVAL;
+    const int max_groups = (conds && conds->max_groups) ? conds->max_groups : WPM_MAX_GROUPS;
+    if (max_groups < 1 || max_groups > WPM_MAX_GROUPS) return WPM_EINVAL;
     if (offset && blocks) return WPM_EINVAL;  // block choices assume a linear span
     if (M > WPM_MAX_M) return WPM_ELIMIT;
     Incidence inc;
@@ -293,17 +295,18 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
         for (int j = 0; j < M; ++j) offj[j] = (char)((offset[j / 32] >> (j % 32)) & 1u);
 
     std::vector<int32_t> crit;
-    int maxp = 0;
+    int maxp = 0;      // over the ridges that can be resident (p - 1 slot words)
+    int maxp_all = 0;  // over all critical ridges (sampling buffers)
     for (int r = 0; r < inc.N; ++r) {
         const int p = inc.parent_off[r + 1] - inc.parent_off[r];
         if (p >= 4) {
             crit.push_back(r);
-            maxp = std::max(maxp, p);
+            maxp_all = std::max(maxp_all, p);
+            if (p - 1 <= WPM_MAX_SLOTS) maxp = std::max(maxp, p);
         }
     }
     const int n_crit = (int)crit.size();
     const int Q = std::max(3, maxp - 1);
-    if (Q > WPM_MAX_SLOTS) return WPM_ELIMIT;
     const int QS = slot_stride_for(Q);
 
     // Sample the vectors the sweep visits (all of them when there are few),
@@ -367,7 +370,7 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
     const uint64_t tail_mask = (T % 64) ? ((1ull << (T % 64)) - 1) : ~0ull;
     // Parent bits of every critical ridge over the samples -> fail sets.
     std::vector<uint64_t> fail((size_t)n_crit * TW, 0);
-    std::vector<uint64_t> pw((size_t)maxp * TW);
+    std::vector<uint64_t> pw((size_t)maxp_all * TW);
     for (int c = 0; c < n_crit; ++c) {
         const int r = crit[c];
         const int p0 = inc.parent_off[r], p = inc.parent_off[r + 1] - p0;
@@ -404,7 +407,9 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
         for (int c = 0; c < n_crit; ++c) {
             if (used[c]) continue;
             const int r = crit[c];
-            if (need_small && inc.parent_off[r + 1] - inc.parent_off[r] > 5) continue;
+            const int pr = inc.parent_off[r + 1] - inc.parent_off[r];
+            if (need_small && pr > 5) continue;
+            if (pr - 1 > WPM_MAX_SLOTS) continue;  // too many parents to be resident
             int g = 0;
             for (int w = 0; w < TW; ++w) g += __builtin_popcountll(fail[(size_t)c * TW + w] & alive[w]);
             if (g > best_gain || (g == best_gain && g == 0 && solo[c] > solo[best])) {
@@ -436,13 +441,25 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
         rest.push_back(c);
     }
     const int64_t alive_full = count_alive();
+    // Resident groups: the filter and the first ridges of the greedy order;
+    // the rest of the critical ridges are deferred to the verification pass.
+    std::vector<int> deferred;
+    const size_t resident_rest = (size_t)(max_groups - 1) * 32;
+    if (rest.size() > resident_rest) {
+        deferred.assign(rest.begin() + (long)resident_rest, rest.end());
+        rest.resize(resident_rest);
+    }
+    for (int c = 0; c < n_crit; ++c)
+        if (!used[c]) deferred.push_back(c);  // more than WPM_MAX_SLOTS + 1 parents
     const int G = 1 + (int)((rest.size() + 31) / 32);
-    if (G > WPM_MAX_GROUPS) return WPM_ELIMIT;
+    int64_t defer_words = 0;
+    for (int c : deferred) defer_words += 1 + (inc.parent_off[crit[c] + 1] - inc.parent_off[crit[c]]);
     const int kp = std::max(k, 7);
     const int RS = ((4 + (G - 1) * QS + W) + 3) & ~3;
     const int nrows = kp + (offset ? 1 : 0);  // the offset row follows the basis rows
     const int64_t props_at = (int64_t)WPM_HDR_WORDS + (int64_t)nrows * RS;
-    const int64_t words = props_at + (nprops ? 2 * (int64_t)nprops + (int64_t)nclasses * (1 + W) : 0);
+    const int64_t defer_at = props_at + (nprops ? 2 * (int64_t)nprops + (int64_t)nclasses * (1 + W) : 0);
+    const int64_t words = defer_at + defer_words;
 
     info->n = n;
     info->m = m;
@@ -456,6 +473,7 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
     info->n_filter = (int)filt.size();
     info->row_words = RS;
     info->max_facets = max_facets;
+    info->n_deferred = (int32_t)deferred.size();
     info->table_words = words;
     info->filter_pass = (double)alive_filter / T;
     info->full_pass = (double)alive_full / T;
@@ -478,6 +496,8 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
     h[HDR_FLAGS] = offset ? HDR_FLAG_OFFSET : 0u;
     h[HDR_PROPS] = nprops ? (uint32_t)props_at : 0u;
     h[HDR_NPROPS] = (uint32_t)nprops;
+    h[HDR_DEFER] = deferred.empty() ? 0u : (uint32_t)defer_at;
+    h[HDR_NDEFER] = (uint32_t)deferred.size();
     uint32_t *rows = table + WPM_HDR_WORDS;
     // slot word (group g, slot q) bit b  <-  parent q of the b-th ridge of group g
     auto place = [&](int c, int word_base, int bit, int slots_used) {
@@ -527,6 +547,14 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
             *pr++ = (uint32_t)conds->class_weight[cls];
             for (int w = 0; w < W; ++w) *pr++ = conds->class_mask[(size_t)cls * W + w];
         }
+    }
+    // deferred ridges: parent count, then the parents' facet indices
+    uint32_t *dr = table + defer_at;
+    for (int c : deferred) {
+        const int r = crit[c];
+        const int p0 = inc.parent_off[r], p = inc.parent_off[r + 1] - p0;
+        *dr++ = (uint32_t)p;
+        for (int q = 0; q < p; ++q) *dr++ = (uint32_t)inc.parents[p0 + q];
     }
     return WPM_OK;
 }

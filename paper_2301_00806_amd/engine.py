@@ -160,6 +160,7 @@ class Prepared:
     offset: Optional[np.ndarray] = None  # [W] offset K* of an affine coset
     props: Optional[list] = None         # [(c0, [(weight, [facet masks])...])...]
     feasible: bool = True                # False: the facet conditions admit no complex
+    max_groups: int = 0                  # resident ridge groups (0: engine maximum)
 
     @property
     def W(self) -> int:
@@ -180,7 +181,7 @@ def prepare(n: int, m: int, lam: Optional[Sequence[int]] = None,
             facets: Optional[Sequence[int]] = None, max_facets: Optional[int] = None,
             seed: int = 0, pack: bool = True, prune: bool = False,
             min_free: int = DEFAULT_MIN_FREE, forced_in=None, forced_out=None,
-            properties=None) -> Prepared:
+            properties=None, max_groups: int = 0) -> Prepared:
     """Candidates (if lambda is given), ridges, kernel basis and packed table.
     With `prune`, the basis is replaced by a convenient basis and the sweep
     visits only the product of its blocks' allowed sets (same results).
@@ -208,7 +209,7 @@ def prepare(n: int, m: int, lam: Optional[Sequence[int]] = None,
         B, blk = convenient_basis(n, m, F, B, k, min_free)
     p = Prepared(n=n, m=m, facets=F, k=k, basis=np.ascontiguousarray(B), N=len(ridges),
                  max_facets=max_facets, blocks=blk, offset=off, props=properties,
-                 feasible=feasible)
+                 feasible=feasible, max_groups=max_groups)
     if pack:
         pack_prepared(p, seed)
     return p
@@ -235,10 +236,11 @@ def pack_prepared(p: Prepared, seed: int = 0) -> None:
 
 def _conditions(p: Prepared):
     """wpm_conditions of a prepared instance (and the arrays it points into)."""
-    if p.offset is None and not p.props:
+    if p.offset is None and not p.props and not p.max_groups:
         return None, None
     keep = []
     c = L.Conditions()
+    c.max_groups = p.max_groups
     if p.offset is not None:
         off = np.ascontiguousarray(p.offset, dtype=np.uint32)
         keep.append(off)
@@ -356,7 +358,8 @@ class DeviceBatch:
             max_slots=max([p.info.slots for p in members] + [4]),
             max_words=max([p.info.W for p in members] + [1]),
             max_kp=max([max(p.k, 7) for p in members] + [7]),
-            d_tables=self.tables.data_ptr(), d_offsets=self.offsets.data_ptr())
+            d_tables=self.tables.data_ptr(), d_offsets=self.offsets.data_ptr(),
+            flags=L.BATCH_DEFERRED if any(p.info.n_deferred for p in members) else 0)
 
     @property
     def vectors(self) -> int:

@@ -15,7 +15,18 @@ HDR = 16
 def header(tab):
     h = [int(v) for v in tab[:HDR]]
     return dict(k=h[1], kp=h[2], M=h[3], W=h[4], G=h[5], QS=h[6], RS=h[7], maxf=h[8],
-                offset=bool(h[11] & 1), props_at=h[12], nprops=h[13])
+                offset=bool(h[11] & 1), props_at=h[12], nprops=h[13], defer_at=h[14], ndefer=h[15])
+
+
+def deferred(tab):
+    """Parent facet indices of each deferred ridge."""
+    h = header(tab)
+    out, at = [], h["defer_at"]
+    for _ in range(h["ndefer"]):
+        p = int(tab[at])
+        out.append([int(v) for v in tab[at + 1:at + 1 + p]])
+        at += 1 + p
+    return out
 
 
 def offset_row(tab):
@@ -86,6 +97,9 @@ def accept(h, v):
     cnt = sum(bin(int(v[koff + w])).count("1") for w in range(h["W"]))
     if not (h["maxf"] == 0 or cnt <= h["maxf"]):
         return False
+    for parents in h.get("deferred", []):
+        if sum((int(v[koff + f // 32]) >> (f % 32)) & 1 for f in parents) > 2:
+            return False
     for c0, cls in h.get("props", []):
         g = c0
         for wgt, mask in cls:
@@ -98,6 +112,7 @@ def accept(h, v):
 def survivors_direct(tab):
     h = header(tab)
     h["props"] = properties(tab)
+    h["deferred"] = deferred(tab)
     R = rows(tab)
     off = offset_row(tab)
     first = 0 if h["offset"] else 1    # x = 0 is K* in a coset, else the empty complex

@@ -139,3 +139,19 @@ def test_stress_large_k_outputs_verified(E):
         except TimeoutError:
             continue
         assert s == want
+
+
+def test_deferred_ridges_verification_pass(E):
+    # one or two resident groups: the other critical ridges are checked on
+    # the survivor records by the verification pass, counts stay exact
+    insts = [i for i in W.batch(E.kdim, count=64) if 14 <= i.meta["k"] <= 22][:12]
+    preps = [E.prepare(i.n, i.m, lam=i.lam, max_groups=1 + (j % 2)) for j, i in enumerate(insts)]
+    for v in (7, 8):
+        F = [(1 << a) | (1 << b) for a, b in itertools.combinations(range(v), 2)]
+        preps.append(E.prepare(2, v, facets=F, max_facets=0, max_groups=1))
+    assert sum(p.info.n_deferred for p in preps) > 0
+    want = oracle_sets(preps)
+    for mode, cbits in ((2, 9), (0, 7)):
+        res, sets = run(E, preps, mode=mode, cbits=cbits)
+        assert sets == want
+        assert list(res.counts) == [len(w) for w in want] and res.total == sum(len(w) for w in want)

@@ -183,3 +183,25 @@ def test_build_queue_groups_and_counts():
     assert per[4] == 0 and per.sum() == len(items)
     for i in range(len(k)):
         assert (items["instance"] == i).sum() == per[i]
+
+
+@pytest.mark.parametrize("case", _instances_small(), ids=lambda c: c[0])
+def test_deferred_ridges_keep_table_semantics(case):
+    # only the filter group (or two groups) resident: the other critical
+    # ridges are listed for the verification pass
+    name, n, m, lam, facets = case
+    for mg in (1, 2):
+        p = E.prepare(n, m, lam=lam, facets=facets, max_groups=mg)
+        assert p.info.groups <= mg
+        assert p.info.n_deferred >= max(0, p.info.n_crit - 32 * mg)
+        want = O.enumerate_wpm(n, [int(f) for f in p.facets], p.max_facets)
+        got_x = TS.survivors_direct(p.table)
+        assert sorted(TS.facets_of_x(p.basis, p.facets, x) for x in got_x) == want
+
+
+def test_many_parents_are_deferred_not_rejected():
+    # K_11: every vertex (ridge) has 10 parents, more than the slot words hold
+    F = [(1 << a) | (1 << b) for a, b in itertools.combinations(range(11), 2)]
+    p = E.prepare(2, 11, facets=F, max_facets=0, pack=False)
+    E.pack_prepared(p)
+    assert p.info.n_deferred == 11 and p.info.groups == 1 and p.info.n_filter == 0
