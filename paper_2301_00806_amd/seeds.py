@@ -77,8 +77,9 @@ def sliced_sweep(p, cbits: int = 12, wg: int = 256, cap: int = 1 << 24,
     """Sweep one (pruned) instance in slices of at most about max_items items:
     each slice fixes the choices of the highest blocks, so its queue is the
     product of the remaining blocks' choices (the table is the same for every
-    slice).  Counts and records accumulate on the device.  Returns the result
-    list of the instance."""
+    slice).  Each slice's results are collected before the next launch, so
+    the record buffer only ever holds one slice.  Returns the result list of
+    the instance."""
     import itertools
     batch = E.DeviceBatch([p])
     sw = E.Sweeper(batch, cap=cap)
@@ -98,6 +99,7 @@ def sliced_sweep(p, cbits: int = 12, wg: int = 256, cap: int = 1 << 24,
     top = list(range(nb - fixed, nb))
     combos = list(itertools.product(*[range(int(blk.count[b])) for b in top])) if fixed else [()]
     t0 = time.perf_counter()
+    results = []
     for si, digits in enumerate(combos):
         if blk is not None:
             part = L.Blocks()
@@ -109,15 +111,12 @@ def sliced_sweep(p, cbits: int = 12, wg: int = 256, cap: int = 1 << 24,
         else:
             items = E.build_queue(np.array([p.k], np.int32), cbits, wg)
         sw.set_items(items, segments=[E.Segment(cls, 0, len(items))])
-        sw.launch(L.SCHED_DYNAMIC, wg_size=wg, accumulate=si > 0)
+        sw.launch(L.SCHED_DYNAMIC, wg_size=wg)
+        results.extend(sw.collect()[0])   # raises on a record-buffer overflow
         if log and (si % max(1, len(combos) // 20) == 0 or si == len(combos) - 1):
-            sw.torch.cuda.synchronize()
-            log(f"slice {si + 1}/{len(combos)} ({len(items)} items), "
+            log(f"slice {si + 1}/{len(combos)} ({len(items)} items), {len(results)} complexes, "
                 f"{time.perf_counter() - t0:.1f}s")
-    res = sw.result()
-    if res.slots > cap:
-        raise L.WpmError("sliced sweep (survivor buffer overflow)", L.WPM_ECAP)
-    return sw.collect()[0]
+    return sorted(results)
 
 
 def gpu_enumerator(cbits: int = 12, wg: int = 256, prune: bool = False, cap: int = 1 << 24,
@@ -145,6 +144,34 @@ def gpu_enumerator(cbits: int = 12, wg: int = 256, prune: bool = False, cap: int
     return run
 
 
+def save_complexes(path: str, sets: Sequence[Sequence[int]]) -> None:
+    """Store a list of complexes (facet mask tuples) as offsets + facets."""
+    offs, fac = _pack(sets)
+    np.savez_compressed(path, offsets=offs, facets=fac[:int(offs[-1])])
+
+
+def load_complexes(path: str) -> List[Complex]:
+    z = np.load(path)
+    offs, fac = z["offsets"], z["facets"]
+    return [tuple(int(v) for v in fac[offs[i]:offs[i + 1]]) for i in range(len(offs) - 1)]
+
+
+def filter_report(n: int, per_orbit: Sequence[Sequence[Sequence[int]]]) -> SeedReport:
+    """Lines 7 to 15 of the algorithm from the swept complexes of each orbit."""
+    m = n + 4
+    union = sorted({tuple(sorted(K)) for s in per_orbit for K in s})
+    flags = complex_filters(n, m, union)
+    want = L.CX_FULL_PICARD | L.CX_SEED
+    kept = [K for K, f in zip(union, flags) if (int(f) & want) == want]
+    cls, num = iso_classes(m, kept)
+    reps = [None] * num
+    for K, c in zip(kept, cls):
+        if reps[c] is None:
+            reps[c] = K
+    return SeedReport(n=n, orbits=len(per_orbit), max_k=0, line7=len(union), line13=len(kept),
+                      line15=num, representatives=reps)
+
+
 def colorable_seeds_pic4(n: int, enumerate_sets: Optional[Callable] = None,
                          prune: bool = False, min_free: int = E.DEFAULT_MIN_FREE,
                          max_orbits: int = 0) -> SeedReport:
@@ -165,24 +192,17 @@ def colorable_seeds_pic4(n: int, enumerate_sets: Optional[Callable] = None,
     sets = run(preps)
     t["enumerate"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    union = sorted({tuple(sorted(K)) for s in sets for K in s})
-    flags = complex_filters(n, m, union)
-    want = L.CX_FULL_PICARD | L.CX_SEED
-    kept = [K for K, f in zip(union, flags) if (int(f) & want) == want]
-    cls, num = iso_classes(m, kept)
-    reps = [None] * num
-    for K, c in zip(kept, cls):
-        if reps[c] is None:
-            reps[c] = K
+    rep = filter_report(n, sets)
     t["filters"] = time.perf_counter() - t0
-    return SeedReport(n=n, orbits=len(lams), max_k=max(p.k for p in preps), line7=len(union),
-                      line13=len(kept), line15=num, representatives=reps, seconds=t)
+    rep.orbits, rep.max_k, rep.seconds = len(lams), max(p.k for p in preps), t
+    return rep
 
 
 def main(argv=None) -> None:
     """Run the pipeline for the given dimensions and print one JSON line each."""
     import argparse
     import json
+    import sys
     ap = argparse.ArgumentParser(description="Algorithm 4.4 (Picard number 4) up to the "
                                              "isomorphism step, on the GPU sweep")
     ap.add_argument("n", type=int, nargs="+")
@@ -192,9 +212,29 @@ def main(argv=None) -> None:
     ap.add_argument("--sliced", action="store_true",
                     help="sweep each orbit in slices over its highest blocks (large n)")
     ap.add_argument("--orbits", type=int, default=0, help="only the first N orbits (timing)")
+    ap.add_argument("--only-orbit", type=int, default=-1,
+                    help="sweep only this orbit (0-based) and --save its complexes")
+    ap.add_argument("--save", default="", help="file for the swept complexes (with --only-orbit)")
+    ap.add_argument("--load", nargs="*", default=[],
+                    help="files of saved orbit results: unite them and run the filters")
     args = ap.parse_args(argv)
-    import sys
     log = lambda msg: print(f"[seeds] {msg}", file=sys.stderr, flush=True)
+    if args.only_orbit >= 0 or args.load:
+        n = args.n[0]
+        if args.only_orbit >= 0:
+            lam = E.idcm_orbits(n)[args.only_orbit]
+            p = E.prepare(n, n + 4, lam=lam, prune=args.prune,
+                          min_free=args.min_free or E.DEFAULT_MIN_FREE)
+            log(f"orbit {args.only_orbit}: k={p.k}, {p.visited:.3e} vectors")
+            sets = sliced_sweep(p, log=log) if args.sliced else E.sweep([p])[1][0]
+            save_complexes(args.save, sets)
+            print(json.dumps({"n": n, "orbit": args.only_orbit, "k": p.k, "complexes": len(sets)}),
+                  flush=True)
+            return
+        rep = filter_report(n, [load_complexes(f) for f in args.load])
+        print(json.dumps({"n": n, "orbits_loaded": len(args.load), "line7": rep.line7,
+                          "line13": rep.line13, "line15": rep.line15}), flush=True)
+        return
     for n in args.n:
         run = gpu_enumerator(prune=args.prune, per_instance=True, log=log, sliced=args.sliced)
         rep = colorable_seeds_pic4(n, enumerate_sets=run, prune=args.prune,

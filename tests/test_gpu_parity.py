@@ -151,7 +151,10 @@ def test_deferred_ridges_verification_pass(E):
         preps.append(E.prepare(2, v, facets=F, max_facets=0, max_groups=1))
     assert sum(p.info.n_deferred for p in preps) > 0
     want = oracle_sets(preps)
+    # with one resident group every vector of K_8 is a candidate (its ridges
+    # have 7 parents, too many for the filter): records before verification
+    # exceed the default buffer
     for mode, cbits in ((2, 9), (0, 7)):
-        res, sets = run(E, preps, mode=mode, cbits=cbits)
+        res, sets = run(E, preps, mode=mode, cbits=cbits, cap=1 << 24)
         assert sets == want
         assert list(res.counts) == [len(w) for w in want] and res.total == sum(len(w) for w in want)

@@ -43,3 +43,15 @@ def test_table2_line15_on_gpu(S, n):
     # the pruned sweep reaches the same classes
     if n in (4, 6):
         assert S.colorable_seeds_pic4(n, prune=True).line15 == TABLE2_LINE15[n]
+
+
+def test_sliced_sweep_equals_one_sweep(S):
+    from paper_2301_00806_amd import engine as E
+    lams = E.idcm_orbits(6)
+    p = E.prepare(6, 10, lam=lams[0], prune=True, min_free=7)
+    assert p.blocks.num_blocks >= 3
+    whole = E.sweep([p], cbits=12)[1][0]
+    logs = []
+    sliced = S.sliced_sweep(p, max_items=64, log=logs.append)
+    print(f"[gpu] sliced sweep: {len(logs)} progress lines, {len(sliced)} complexes", flush=True)
+    assert sliced == sorted(whole)

@@ -77,3 +77,19 @@ def test_filters_reject_bad_input():
     assert st == L.WPM_EINVAL
     assert L.lib().wpm_iso_classes(17, 0, None, None, E._ptr(np.zeros(1, np.int64), L.c_i64p),
                                    E._ptr(np.zeros(1, np.int64), L.c_i64p)) == L.WPM_EINVAL
+
+
+def test_saved_orbit_results_give_the_same_report(tmp_path):
+    n, m = 4, 8
+    lams = E.idcm_orbits(n)
+    per = [O.enumerate_wpm(n, O.candidates(n, m, lam), O.default_max_facets(n, m)) for lam in lams]
+    files = []
+    for i, sets in enumerate(per):
+        f = str(tmp_path / f"orbit{i}.npz")
+        S.save_complexes(f, sets)
+        files.append(f)
+        assert S.load_complexes(f) == [tuple(K) for K in sets]
+    rep = S.filter_report(n, [S.load_complexes(f) for f in files])
+    ref = S.colorable_seeds_pic4(n, enumerate_sets=oracle_enumerator)
+    assert (rep.line7, rep.line13, rep.line15) == (ref.line7, ref.line13, ref.line15) == \
+        (ref.line7, ref.line13, TABLE2_LINE15[n])
