@@ -19,6 +19,7 @@
 // "at most 2 of the slots set" runs on 32 ridges per instruction.
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <vector>
