@@ -97,9 +97,21 @@ def cpu_baseline(preps, budget_s: float):
                     submit()
                 break
     el = time.time() - t0
+    # the same oracle on one thread: instances of the sample in k order, about 5 s
+    one_vec, one_n, t1 = 0.0, 0, time.time()
+    for i in sorted(sample, key=lambda i: preps[i].k)[::max(1, len(sample) // 64)]:
+        if time.time() - t1 > 5.0:
+            break
+        p = preps[i]
+        O.enumerate_wpm(p.n, [int(f) for f in p.facets], p.max_facets)
+        one_vec += float(1 << p.k)
+        one_n += 1
+    el1 = time.time() - t1
     return {"value": done_vec / el, "unit": "kernel vectors/s", "cores": cores, "kind": "oracle",
             "sample": f"{done_n} of the {len(preps)} instances (spread over the k range), "
-                      f"{el:.1f}s wall, one instance per thread; vectors = sum of 2^k"}
+                      f"{el:.1f}s wall, one instance per thread; vectors = sum of 2^k",
+            "single_thread_value": one_vec / el1 if el1 > 0 else None,
+            "single_thread_sample": f"{one_n} instances of that sample in k order, {el1:.1f}s, one thread"}
 
 
 def main():
@@ -125,6 +137,8 @@ def main():
     ap.add_argument("--no-split", action="store_true",
                     help="one launch under the largest kernel template instead of one per class")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-e2e", action="store_true",
+                    help="skip the end-to-end run (table upload, step, collect to facet lists)")
     ap.add_argument("--no-pruned", action="store_true",
                     help="skip the convenient-basis (pruned) sweep of the same batch")
     ap.add_argument("--min-free", type=int, default=0,
@@ -189,9 +203,10 @@ def main():
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        kern_ms, seg_ms = [], {}
+        kern_ms, seg_ms, walls = [], {}, []
         t0 = time.perf_counter()
         for _ in range(steps):
+            ts = time.perf_counter()
             plan = make()                              # scheduling is part of the step
             sw.set_items(plan.items, segments=plan.segments)
             e0.record(stream)
@@ -205,8 +220,10 @@ def main():
             kern_ms.append(e0.elapsed_time(e1))
             for cls, a0, a1 in sw.seg_events:
                 seg_ms.setdefault(cls, []).append(a0.elapsed_time(a1))
+            walls.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
+        timed_plan.medians = (float(np.median(walls)) * 1e3, float(np.median(kern_ms)))
         res = sw.result()
         log(f"{label}: kernel {np.mean(kern_ms):.2f} ms, step {wall * 1e3:.2f} ms, "
             f"{vec / wall:.3e} vectors/s, total WPMs {res.total}, stats {res.stats[:3]}")
@@ -215,6 +232,32 @@ def main():
 
     t_b, k_b, res_b = timed_plan(plan_learned, args.steps, args.warmup, f"learned-{args.learned_policy}")
     seg_ms = dict(timed_plan.seg_ms)
+    step_med, kern_med = timed_plan.medians
+
+    # ---- end to end once: packed tables host -> HBM, one step, records back
+    # and expanded into canonical facet lists by wpm_collect
+    e2e = None
+    if not args.no_e2e:
+        host_tab = batch.tables.cpu().pin_memory()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.tables.copy_(host_tab)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan = plan_learned()
+        sw.set_items(plan.items, segments=plan.segments)
+        sw.launch(plan.mode, wg_size=args.wg, stream=stream)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        cnt_e, words_e, _ = sw.collect_raw()
+        t3 = time.perf_counter()
+        assert np.array_equal(cnt_e, res_b.counts)
+        e2e = {"h2d_ms": (t1 - t0) * 1e3, "step_ms": (t2 - t1) * 1e3, "collect_ms": (t3 - t2) * 1e3,
+               "total_ms": (t3 - t0) * 1e3, "vectors_per_s": vectors / (t3 - t0),
+               "table_bytes": batch.table_bytes, "facet_words": int(len(words_e)),
+               "note": "collect = records to host + expansion to sorted facet lists, 16 host threads"}
+        log(f"end to end: {e2e}")
+        del words_e
     # the dominant launch: the template class holding most of the vectors
     cls_vec = {}
     for p, c in zip(preps, batch.cls):
@@ -296,6 +339,15 @@ def main():
 
     achieved = ALG_OPS_PER_VECTOR * cls_vec[dom] / (dom_ms * 1e-3) / 1e12
     probe = E.valu_probe(0, 4)
+    counters = None
+    cpath = os.path.join(ROOT, "profiles", "sweep_counters.json")
+    if os.path.exists(cpath):
+        import hashlib
+        src = open(os.path.join(ROOT, "paper_2301_00806_amd", "csrc", "sweep_kernel.h"), "rb").read()
+        with open(cpath) as f:
+            cj = json.load(f)
+        if cj.get("kernel_source_sha256") == hashlib.sha256(src).hexdigest() and cj.get("kernel") == dom_name:
+            counters = cj
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "sweep_traffic.json")
     if os.path.exists(tpath):
@@ -313,6 +365,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": t_b * 1e3,
+        "ms_per_step_median": step_med,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -327,6 +380,8 @@ def main():
         "wpm_counts_sha256": __import__("hashlib").sha256(res_b.counts.tobytes()).hexdigest(),
         "wpm_counts_match_oracle": oracle_counts_match(res_b.counts, len(preps)),
         "kernel_ms": k_b,
+        "kernel_ms_median": kern_med,
+        "end_to_end": e2e,
         "schedules": out,
         "pruned": pruned,
         "cost_model": model_err,
@@ -336,7 +391,10 @@ def main():
                      "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved / (INT32_PEAK / 1e12),
                      "traffic": traffic, "kernel": dom_name, "kernel_ms": dom_ms,
                      "vectors_per_launch": cls_vec[dom], "ops_per_vector": ALG_OPS_PER_VECTOR,
-                     "measured_int32_xor_peak": probe / 1e12},
+                     "measured_int32_xor_peak": probe / 1e12,
+                     "executed_frac": None if counters is None else
+                     counters["executed_lane_ops_per_s"] / INT32_PEAK,
+                     "valu_busy": None if counters is None else counters["valu_busy"]},
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(preps, args.cpu_budget)

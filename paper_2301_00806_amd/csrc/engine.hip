@@ -2,8 +2,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -241,12 +243,49 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     return verify(b, d_surv, cap, d_counts, d_total, st);
 }
 
+namespace {
+
+// Run fn(i) for i in [0, num) on up to 16 host threads (dynamic chunks).
+template <class Fn>
+void host_parallel_for(int64_t num, Fn fn) {
+    const int hw = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const int nt = (int)std::min<int64_t>(hw, std::max<int64_t>(1, num));
+    std::atomic<int64_t> next{0};
+    auto work = [&]() {
+        for (;;) {
+            const int64_t a = next.fetch_add(16);
+            if (a >= num) break;
+            for (int64_t i = a; i < std::min(num, a + 16); ++i) fn(i);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (auto &t : th) t.join();
+}
+
+// K = offset + sum of the basis vectors selected by x, as W words.
+inline void expand_x(const wpm_host_instance &in, uint64_t x, uint32_t *K) {
+    const int W = (in.M + 31) / 32;
+    for (int w = 0; w < W; ++w) K[w] = in.offset ? in.offset[w] : 0u;
+    for (uint64_t b = x; b; b &= b - 1) {
+        const int t = __builtin_ctzll(b);
+        for (int w = 0; w < W; ++w) K[w] ^= in.basis[(size_t)t * W + w];
+    }
+}
+
+}  // namespace
+
 int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv, uint64_t cap,
             const uint64_t *d_counts, const uint64_t *d_total, uint64_t *h_counts, uint32_t *h_out,
             int64_t out_cap, int64_t *out_words, int64_t *h_offsets, void *stream) {
     if (num < 0 || !d_counts || !d_total || !h_counts || !out_words || !h_offsets ||
         (num > 0 && !insts))
         return WPM_EINVAL;
+    for (int i = 0; i < num; ++i)
+        if (insts[i].M < 0 || insts[i].M > WPM_MAX_M || insts[i].k < 0 || insts[i].k > WPM_MAX_K ||
+            (insts[i].k > 0 && !insts[i].basis) || (insts[i].M > 0 && !insts[i].facets))
+            return WPM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     uint64_t tot[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(h_counts, d_counts, sizeof(uint64_t) * (size_t)num, hipMemcpyDeviceToHost, st));
@@ -265,51 +304,80 @@ int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv,
     uint64_t sum = 0;
     for (int i = 0; i < num; ++i) sum += h_counts[i];
     if (sum != total) return WPM_EINVAL;  // counts and total disagree: corrupted buffers
-    // group by instance, expand x -> facet list, canonical order
-    std::vector<std::vector<uint64_t>> per(num);
+    // group the records by instance (counting sort; unused slots carry ~0)
+    std::vector<int64_t> start((size_t)num + 1, 0);
     uint64_t found = 0;
     for (uint64_t r = 0; r < slots; ++r) {
         const uint64_t inst = rec[2 * r + 1];
-        if (inst == ~0ull) continue;  // unused slot of a wave's chunk
+        if (inst == ~0ull) continue;
         if (inst >= (uint64_t)num) return WPM_EINVAL;
-        per[inst].push_back(rec[2 * r]);
+        const uint64_t x = rec[2 * r];
+        if (insts[inst].k < 64 && (x >> insts[inst].k)) return WPM_EINVAL;
+        ++start[inst + 1];
         ++found;
     }
     if (found != total) return WPM_EINVAL;
-    int64_t words = 0;
-    std::vector<std::vector<std::vector<uint32_t>>> res(num);
     for (int i = 0; i < num; ++i) {
-        const int M = insts[i].M, W = (M + 31) / 32, k = insts[i].k;
-        auto &ri = res[i];
-        ri.reserve(per[i].size());
-        std::vector<uint32_t> K(W);
-        for (uint64_t x : per[i]) {
-            if (k < 64 && (x >> k)) return WPM_EINVAL;
-            for (int w = 0; w < W; ++w) K[w] = insts[i].offset ? insts[i].offset[w] : 0u;
-            for (uint64_t b = x; b; b &= b - 1) {
-                const int t = __builtin_ctzll(b);
-                for (int w = 0; w < W; ++w) K[w] ^= insts[i].basis[(size_t)t * W + w];
-            }
-            std::vector<uint32_t> f;
-            for (int w = 0; w < W; ++w)
-                for (uint32_t v = K[w]; v; v &= v - 1) f.push_back(insts[i].facets[w * 32 + __builtin_ctz(v)]);
-            std::sort(f.begin(), f.end());
-            words += 1 + (int64_t)f.size();
-            ri.push_back(std::move(f));
-        }
-        std::sort(ri.begin(), ri.end());
+        if ((uint64_t)start[i + 1] != h_counts[i]) return WPM_EINVAL;
+        start[i + 1] += start[i];
     }
+    std::vector<uint64_t> xs((size_t)found);
+    {
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (uint64_t r = 0; r < slots; ++r)
+            if (rec[2 * r + 1] != ~0ull) xs[(size_t)fill[rec[2 * r + 1]]++] = rec[2 * r];
+    }
+    // words per instance: one length word plus |K| facets per complex
+    std::vector<int64_t> iw((size_t)num, 0);
+    host_parallel_for(num, [&](int64_t i) {
+        uint32_t K[WPM_MAX_M / 32];
+        const int W = (insts[i].M + 31) / 32;
+        int64_t w = 0;
+        for (int64_t r = start[i]; r < start[i + 1]; ++r) {
+            expand_x(insts[i], xs[(size_t)r], K);
+            w += 1;
+            for (int q = 0; q < W; ++q) w += __builtin_popcount(K[q]);
+        }
+        iw[(size_t)i] = w;
+    });
+    int64_t words = 0;
+    for (int i = 0; i < num; ++i) {
+        h_offsets[i] = words;
+        words += iw[(size_t)i];
+    }
+    h_offsets[num] = words;
     *out_words = words;
     if (!h_out || out_cap < words) return WPM_ECAP;
-    int64_t w = 0;
-    for (int i = 0; i < num; ++i) {
-        h_offsets[i] = w;
-        for (auto &f : res[i]) {
-            h_out[w++] = (uint32_t)f.size();
-            for (uint32_t v : f) h_out[w++] = v;
+    // expand each complex to its sorted facet list; order the complexes of an
+    // instance lexicographically (the canonical form)
+    host_parallel_for(num, [&](int64_t i) {
+        const int64_t n_i = start[i + 1] - start[i];
+        if (!n_i) return;
+        const int W = (insts[i].M + 31) / 32;
+        std::vector<uint32_t> flat;
+        std::vector<int64_t> beg((size_t)n_i + 1, 0);
+        flat.reserve((size_t)(iw[(size_t)i] - n_i));
+        uint32_t K[WPM_MAX_M / 32];
+        for (int64_t r = 0; r < n_i; ++r) {
+            expand_x(insts[i], xs[(size_t)(start[i] + r)], K);
+            const size_t b0 = flat.size();
+            for (int w = 0; w < W; ++w)
+                for (uint32_t v = K[w]; v; v &= v - 1) flat.push_back(insts[i].facets[w * 32 + __builtin_ctz(v)]);
+            std::sort(flat.begin() + (long)b0, flat.end());
+            beg[(size_t)r + 1] = (int64_t)flat.size();
         }
-    }
-    h_offsets[num] = w;
+        std::vector<int64_t> idx((size_t)n_i);
+        for (int64_t r = 0; r < n_i; ++r) idx[(size_t)r] = r;
+        std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+            return std::lexicographical_compare(flat.begin() + beg[a], flat.begin() + beg[a + 1],
+                                                flat.begin() + beg[b], flat.begin() + beg[b + 1]);
+        });
+        int64_t w = h_offsets[i];
+        for (int64_t r : idx) {
+            h_out[w++] = (uint32_t)(beg[r + 1] - beg[r]);
+            for (int64_t q = beg[r]; q < beg[r + 1]; ++q) h_out[w++] = flat[(size_t)q];
+        }
+    });
     return WPM_OK;
 }
 

@@ -590,6 +590,23 @@ class Sweeper:
 
     def collect(self, stream=None) -> List[List[Tuple[int, ...]]]:
         """Per instance, the canonical list of results (sorted tuples of facet masks)."""
+        _, out, offs = self.collect_raw(stream)
+        res = []
+        for i in range(len(self.batch.preps)):
+            a, b = int(offs[i]), int(offs[i + 1])
+            lst = []
+            w = a
+            while w < b:
+                ln = int(out[w])
+                lst.append(tuple(int(v) for v in out[w + 1:w + 1 + ln]))
+                w += 1 + ln
+            res.append(lst)
+        return res
+
+    def collect_raw(self, stream=None):
+        """wpm_collect as flat arrays: (counts, words, offsets[num + 1]).
+        Instance i's complexes are words[offsets[i]:offsets[i+1]], each as its
+        facet count followed by its facet masks, in canonical order."""
         torch = self.torch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -623,17 +640,7 @@ class Sweeper:
         st = lib.wpm_collect(*args, _ptr(out), words.value, ctypes.byref(words),
                              _ptr(offs, L.c_i64p), ctypes.c_void_p(stream.cuda_stream))
         L.check("wpm_collect", st)
-        res = []
-        for i in range(len(preps)):
-            a, b = int(offs[i]), int(offs[i + 1])
-            lst = []
-            w = a
-            while w < b:
-                ln = int(out[w])
-                lst.append(tuple(int(v) for v in out[w + 1:w + 1 + ln]))
-                w += 1 + ln
-            res.append(lst)
-        return res
+        return h_counts[:len(preps)], out[:words.value], offs
 
 
 def sweep(preps: Sequence[Prepared], mode: int = L.SCHED_DYNAMIC, cbits: int = 12,
