@@ -147,7 +147,7 @@ def main():
                     help="also run a plain 256 MiB device copy (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the engine runs on a single device "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 

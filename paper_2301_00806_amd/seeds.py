@@ -4,13 +4,14 @@ For Picard number 4 and dimension n - 1 (m = n + 4):
   1. one characteristic matrix per IDCM orbit (wpm_idcm_orbits);
   2. for each, every weak pseudo-manifold with facets in F(lambda) and at
      most f(n) facets (the GPU sweep; the upper-bound property of Section
-     4.2) -- the union is the set K(n, 4) of the algorithm's line 7;
+     4.2) -- the union is the set K(n, 4), Table 2's first row;
   3. discard complexes with Pic(K) < 4 or failing the seedness condition
-     (wpm_complex_filters) -- line 13;
-  4. one representative per isomorphism class (wpm_iso_classes) -- line 15.
+     (wpm_complex_filters) -- Table 2's second row;
+  4. one representative per isomorphism class (wpm_iso_classes) -- Table 2's
+     third row.
 The PL-sphere test of the algorithm's last step is not part of this engine.
-Counts at lines 7 and 13 count labelled complexes, so they depend on which
-representative each orbit gets; line 15 does not.
+The first two rows count labelled complexes, so they depend on which
+representative each orbit gets; the isomorphism classes do not.
 """
 from __future__ import annotations
 
@@ -65,9 +66,9 @@ class SeedReport:
     n: int
     orbits: int
     max_k: int
-    line7: int                 # |K(n,4)|: union of the sweeps' outputs
-    line13: int                # after the Picard-number and seedness filters
-    line15: int                # isomorphism classes
+    union: int                 # |K(n,4)|: union of the sweeps' outputs
+    filtered: int              # after the Picard-number and seedness filters
+    classes: int               # isomorphism classes
     representatives: List[Complex] = field(default_factory=list)
     seconds: dict = field(default_factory=dict)
 
@@ -168,8 +169,8 @@ def filter_report(n: int, per_orbit: Sequence[Sequence[Sequence[int]]]) -> SeedR
     for K, c in zip(kept, cls):
         if reps[c] is None:
             reps[c] = K
-    return SeedReport(n=n, orbits=len(per_orbit), max_k=0, line7=len(union), line13=len(kept),
-                      line15=num, representatives=reps)
+    return SeedReport(n=n, orbits=len(per_orbit), max_k=0, union=len(union), filtered=len(kept),
+                      classes=num, representatives=reps)
 
 
 def colorable_seeds_pic4(n: int, enumerate_sets: Optional[Callable] = None,
@@ -232,16 +233,16 @@ def main(argv=None) -> None:
                   flush=True)
             return
         rep = filter_report(n, [load_complexes(f) for f in args.load])
-        print(json.dumps({"n": n, "orbits_loaded": len(args.load), "line7": rep.line7,
-                          "line13": rep.line13, "line15": rep.line15}), flush=True)
+        print(json.dumps({"n": n, "orbits_loaded": len(args.load), "union": rep.union,
+                          "filtered": rep.filtered, "classes": rep.classes}), flush=True)
         return
     for n in args.n:
         run = gpu_enumerator(prune=args.prune, per_instance=True, log=log, sliced=args.sliced)
         rep = colorable_seeds_pic4(n, enumerate_sets=run, prune=args.prune,
                                    min_free=args.min_free or E.DEFAULT_MIN_FREE,
                                    max_orbits=args.orbits)
-        print(json.dumps({"n": n, "orbits": rep.orbits, "max_k": rep.max_k, "line7": rep.line7,
-                          "line13": rep.line13, "line15": rep.line15,
+        print(json.dumps({"n": n, "orbits": rep.orbits, "max_k": rep.max_k, "union": rep.union,
+                          "filtered": rep.filtered, "classes": rep.classes,
                           "seconds": {k: round(v, 2) for k, v in rep.seconds.items()}}),
               flush=True)
 

@@ -1,6 +1,6 @@
 """Algorithm 4.4 up to its isomorphism step with the GPU sweep: Table 2's
-line 15 (isomorphism classes of seeds of Picard number 4 supporting an IDCM)
-for n = 2..7, and, for n <= 5, the same labelled sets at lines 7 and 13 as the
+third row (isomorphism classes of seeds of Picard number 4 supporting an IDCM)
+for n = 2..7, and, for n <= 5, the same labelled sets in its first two rows as the
 pipeline run on the oracle's enumeration."""
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -8,7 +8,7 @@ from concurrent.futures import ThreadPoolExecutor
 import pytest
 
 import oracle as O
-from test_seeds import TABLE2_LINE15
+from test_seeds import TABLE2_CLASSES
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -30,19 +30,19 @@ def oracle_enumerator(preps):
 
 
 @pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 7])
-def test_table2_line15_on_gpu(S, n):
+def test_table2_classes_on_gpu(S, n):
     print(f"[gpu] Algorithm 4.4 for n={n}", flush=True)
     rep = S.colorable_seeds_pic4(n)
-    print(f"[gpu] n={n}: line7 {rep.line7} line13 {rep.line13} line15 {rep.line15} "
+    print(f"[gpu] n={n}: union {rep.union} filtered {rep.filtered} classes {rep.classes} "
           f"{rep.seconds}", flush=True)
-    assert rep.line15 == TABLE2_LINE15[n]
+    assert rep.classes == TABLE2_CLASSES[n]
     if n <= 5:
         ref = S.colorable_seeds_pic4(n, enumerate_sets=oracle_enumerator)
-        assert (rep.line7, rep.line13) == (ref.line7, ref.line13)
+        assert (rep.union, rep.filtered) == (ref.union, ref.filtered)
         assert rep.representatives == ref.representatives
     # the pruned sweep reaches the same classes
     if n in (4, 6):
-        assert S.colorable_seeds_pic4(n, prune=True).line15 == TABLE2_LINE15[n]
+        assert S.colorable_seeds_pic4(n, prune=True).classes == TABLE2_CLASSES[n]
 
 
 def test_sliced_sweep_equals_one_sweep(S):

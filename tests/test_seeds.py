@@ -1,6 +1,6 @@
 """Filters after the sweep (Algorithm 4.4) on the host: the engine's
 Picard/seedness flags and isomorphism classes against the oracle's plain
-definitions (oracle/seeds.py), and Table 2's line 15 (isomorphism classes of
+definitions (oracle/seeds.py), and Table 2's third row (isomorphism classes of
 seeds of Picard number 4 supporting an IDCM) for n = 2, 3, 4 with the oracle's
 enumeration standing in for the GPU sweep."""
 import json
@@ -15,7 +15,7 @@ from paper_2301_00806_amd import _lib as L
 from paper_2301_00806_amd import engine as E
 from paper_2301_00806_amd import seeds as S
 
-TABLE2_LINE15 = {2: 2, 3: 5, 4: 49, 5: 256, 6: 1791, 7: 2194, 8: 1401, 9: 381, 10: 56}
+TABLE2_CLASSES = {2: 2, 3: 5, 4: 49, 5: 256, 6: 1791, 7: 2194, 8: 1401, 9: 381, 10: 56}
 
 
 def oracle_enumerator(preps):
@@ -61,10 +61,10 @@ def test_iso_classes_match_oracle_partition(n, sample):
 
 
 @pytest.mark.parametrize("n", [2, 3, 4])
-def test_table2_line15_with_oracle_enumeration(n):
+def test_table2_classes_with_oracle_enumeration(n):
     rep = S.colorable_seeds_pic4(n, enumerate_sets=oracle_enumerator)
     assert rep.orbits == [7, 16, 28][n - 2]
-    assert rep.line15 == TABLE2_LINE15[n]
+    assert rep.classes == TABLE2_CLASSES[n]
 
 
 def test_filters_reject_bad_input():
@@ -91,5 +91,5 @@ def test_saved_orbit_results_give_the_same_report(tmp_path):
         assert S.load_complexes(f) == [tuple(K) for K in sets]
     rep = S.filter_report(n, [S.load_complexes(f) for f in files])
     ref = S.colorable_seeds_pic4(n, enumerate_sets=oracle_enumerator)
-    assert (rep.line7, rep.line13, rep.line15) == (ref.line7, ref.line13, ref.line15) == \
-        (ref.line7, ref.line13, TABLE2_LINE15[n])
+    assert (rep.union, rep.filtered, rep.classes) == (ref.union, ref.filtered, ref.classes) == \
+        (ref.union, ref.filtered, TABLE2_CLASSES[n])
