@@ -92,7 +92,7 @@ int zero(void *p, int64_t n, hipStream_t st) {
 }
 
 int pick_gm(int g) { return g <= 2 ? 2 : g <= 4 ? 4 : g <= 8 ? 8 : 16; }
-int pick_wm(int w) { return w <= 4 ? 4 : w <= 16 ? 16 : 32; }
+int pick_wm(int w) { return w <= 4 ? 4 : w <= 10 ? 10 : w <= 16 ? 16 : 32; }
 
 hipError_t launch(int gm, int qs, int wm, dim3 grid, dim3 block, size_t lds, hipStream_t st,
                   const uint32_t *tables, const int64_t *offsets, const wpm_item *items,

@@ -21,10 +21,12 @@ hipError_t launch_sweep_g8(int qs, int wm, dim3 grid, dim3 block, size_t lds, hi
                             const KArgs &a) {
     if (qs == 4) {
         if (wm == 4) return launch_one<4, 4>(grid, block, lds, st, tables, offsets, items, a);
+        if (wm == 10) return launch_one<4, 10>(grid, block, lds, st, tables, offsets, items, a);
         if (wm == 16) return launch_one<4, 16>(grid, block, lds, st, tables, offsets, items, a);
         return launch_one<4, 32>(grid, block, lds, st, tables, offsets, items, a);
     }
     if (wm == 4) return launch_one<8, 4>(grid, block, lds, st, tables, offsets, items, a);
+    if (wm == 10) return launch_one<8, 10>(grid, block, lds, st, tables, offsets, items, a);
     if (wm == 16) return launch_one<8, 16>(grid, block, lds, st, tables, offsets, items, a);
     return launch_one<8, 32>(grid, block, lds, st, tables, offsets, items, a);
 }
@@ -32,10 +34,12 @@ hipError_t launch_sweep_g8(int qs, int wm, dim3 grid, dim3 block, size_t lds, hi
 hipError_t occupancy_sweep_g8(int qs, int wm, int *nb, int block, size_t lds) {
     if (qs == 4) {
         if (wm == 4) return occ_one<4, 4>(nb, block, lds);
+        if (wm == 10) return occ_one<4, 10>(nb, block, lds);
         if (wm == 16) return occ_one<4, 16>(nb, block, lds);
         return occ_one<4, 32>(nb, block, lds);
     }
     if (wm == 4) return occ_one<8, 4>(nb, block, lds);
+    if (wm == 10) return occ_one<8, 10>(nb, block, lds);
     if (wm == 16) return occ_one<8, 16>(nb, block, lds);
     return occ_one<8, 32>(nb, block, lds);
 }

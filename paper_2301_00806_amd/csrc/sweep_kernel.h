@@ -138,8 +138,15 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Occupancy: up to 8 ridge groups and 10 facet words (the bulk of the
+// Picard-number-4 instances with n <= 8) are compiled for 7 waves per SIMD
+// (at most 72 VGPRs); the few spills that costs sit in the per-item set-up and
+// the block boundary, not in the 64-step loop.  Measured on the 16384-instance
+// batch: 5, 6, 7 and 8 waves gave 205.8, 191.1, 180.4 and 187.3 ms.  Larger
+// templates keep the compiler's own register budget.
 template <int GM, int QS, int WM>
-__global__ __launch_bounds__(512) void sweep_kernel(const uint32_t *__restrict__ tables,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((WM <= 10 && GM <= 8) ? 7 : 1)))
+void sweep_kernel(const uint32_t *__restrict__ tables,
                                                      const int64_t *__restrict__ offsets,
                                                      const wpm_item *__restrict__ items, KArgs a_in) {
     // LDS: [64][RS] U table (state contribution of every 6-bit low vector),

@@ -303,7 +303,7 @@ def _gm(groups: int) -> int:
 
 
 def _wm(words: int) -> int:
-    return 4 if words <= 4 else 16 if words <= 16 else 32
+    return 4 if words <= 4 else 10 if words <= 10 else 16 if words <= 16 else 32
 
 
 def template_class(info) -> int:

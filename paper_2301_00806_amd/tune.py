@@ -28,7 +28,7 @@ def shape_key(batch: "E.DeviceBatch") -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     b = batch.c_batch
     gm = 2 if b.max_groups <= 2 else 4 if b.max_groups <= 4 else 8 if b.max_groups <= 8 else 16
-    wm = 4 if b.max_words <= 4 else 16 if b.max_words <= 16 else 32
+    wm = 4 if b.max_words <= 4 else 10 if b.max_words <= 10 else 16 if b.max_words <= 16 else 32
     lv = int(np.log2(max(1.0, batch.visited / max(1, len(batch.preps)))))
     pr = "/pruned" if batch.blocks is not None else ""
     return f"{arch}/gm{gm}/qs{b.max_slots}/wm{wm}/v{lv}{pr}"
