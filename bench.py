@@ -38,11 +38,23 @@ INT32_PEAK = 256 * 128 * 2.4e9
 ALG_OPS_PER_VECTOR = 7             # fast filter: 4 XOR + 2 threshold ops + 1 compare
 
 
-def build_workload(count: int, seed_start: int = 0):
+WORKLOADS = {
+    "learned": "learned-scheduler batch: {count} lambda = [I_n | 4 uniform], n = 5..8, m = n + 4, k <= 36",
+    "batch": "batch: {count} lambda = [I_n | 4 uniform], n = 4..7, m = n + 4, 12 <= k <= 32",
+    "stress": "stress: {count} random 0.75-dense subsets of the 7-subsets of [11], 32 <= k <= 40",
+}
+
+
+def build_workload(count: int, workload: str = "learned", seed_start: int = 0):
     import wpm_inputs as W
     from paper_2301_00806_amd import engine as E
     t = time.time()
-    insts = W.learned(E.kdim, count=count, start=seed_start)
+    if workload == "learned":
+        insts = W.learned(E.kdim, count=count, start=seed_start)
+    elif workload == "batch":
+        insts = W.batch(E.kdim, count=count, start=seed_start)
+    else:
+        insts = W.stress(E.kdim, count=count, start=seed_start)
     log(f"selected {len(insts)} instances in {time.time() - t:.1f}s")
     t = time.time()
     preps = E.prepare_many(insts)
@@ -119,7 +131,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--instances", type=int, default=16384)
+    ap.add_argument("--workload", default="learned", choices=sorted(WORKLOADS),
+                    help="learned (the headline), batch or stress")
+    ap.add_argument("--instances", type=int, default=0, help="0 = the workload's own size")
     ap.add_argument("--cbits", type=int, default=0, help="lane chunk bits (0 = autotuned)")
     ap.add_argument("--wg", type=int, default=0, help="workgroup size (0 = autotuned)")
     ap.add_argument("--max-items", type=int, default=0)
@@ -158,7 +172,9 @@ def main():
     cus, clk_khz, lds = E.device_query()
     log(f"device: {cus} CUs, wallclock {clk_khz} kHz, LDS/block {lds}")
 
-    insts, preps = build_workload(args.instances)
+    if args.instances == 0:
+        args.instances = {"learned": 16384, "batch": 4096, "stress": 64}[args.workload]
+    insts, preps = build_workload(args.instances, args.workload)
     batch = E.DeviceBatch(preps)
     vectors = batch.vectors
     log(f"sum 2^k = {vectors:.4e}; tables {batch.table_bytes / 1e6:.1f} MB in HBM")
@@ -346,7 +362,8 @@ def main():
         src = open(os.path.join(ROOT, "paper_2301_00806_amd", "csrc", "sweep_kernel.h"), "rb").read()
         with open(cpath) as f:
             cj = json.load(f)
-        if cj.get("kernel_source_sha256") == hashlib.sha256(src).hexdigest() and cj.get("kernel") == dom_name:
+        if (cj.get("kernel_source_sha256") == hashlib.sha256(src).hexdigest() and cj.get("kernel") == dom_name
+                and cj.get("vectors") == float(cls_vec[dom])):
             counters = cj
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "sweep_traffic.json")
@@ -355,7 +372,8 @@ def main():
         src = open(os.path.join(ROOT, "paper_2301_00806_amd", "csrc", "sweep_kernel.h"), "rb").read()
         with open(tpath) as f:
             tr = json.load(f)
-        if tr.get("kernel_source_sha256") == hashlib.sha256(src).hexdigest() and tr.get("kernel") == dom_name:
+        if (tr.get("kernel_source_sha256") == hashlib.sha256(src).hexdigest() and tr.get("kernel") == dom_name
+                and tr.get("vectors") == float(cls_vec[dom])):
             traffic = tr.get("bytes_per_launch")
     line = {
         "metric": "kernel vectors checked/sec + WPM count (bit-exact); batched+learned vs plain",
@@ -370,15 +388,15 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
-        "data": "synthetic (seeded SplitMix64 characteristic matrices)",
-        "config": {"workload": "learned-scheduler batch: 16384 lambda = [I_n | 4 uniform], "
-                               "n = 5..8, m = n + 4, k <= 36",
+        "data": "synthetic (seeded SplitMix64 inputs)",
+        "config": {"workload": WORKLOADS[args.workload].format(count=len(preps)),
                    "instances": len(preps), "sum_2k": vectors, "cbits": args.cbits,
                    "wg_size": args.wg,
                    "schedule": f"learned: {args.learned_policy}, LPT on MLP-predicted cost"},
         "wpm_total": int(res_b.total),
         "wpm_counts_sha256": __import__("hashlib").sha256(res_b.counts.tobytes()).hexdigest(),
-        "wpm_counts_match_oracle": oracle_counts_match(res_b.counts, len(preps)),
+        "wpm_counts_match_oracle": oracle_counts_match(res_b.counts, len(preps))
+        if args.workload == "learned" else None,
         "kernel_ms": k_b,
         "kernel_ms_median": kern_med,
         "end_to_end": e2e,
