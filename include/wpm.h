@@ -62,7 +62,7 @@ enum {
 #define WPM_MAX_GROUPS 16   /* 32-ridge groups of critical ridges (<= 512 ridges) */
 #define WPM_MAX_SLOTS 8     /* parents-1 of a critical ridge */
 #define WPM_LOW_BITS 6      /* Gray steps unrolled per block: 2^6 */
-#define WPM_TABLE_ROWS 64   /* low-part rows staged per instance: 2^6 */
+#define WPM_TABLE_ROWS 32   /* Gray-bit lookup rows staged per instance: 4 tables of 2^3 */
 
 /* Human-readable text of a status code (static storage). */
 const char *wpm_strerror(int status);
@@ -446,9 +446,10 @@ int wpm_persistent_grid(const wpm_batch *batch, int32_t wg_size, int32_t *grid);
  *   d_total     [2] uint64 device: [0] total results, [1] record slots used
  *               ([1] > cap: the caller needs a larger buffer and wpm_collect
  *               returns WPM_ECAP; counts stay exact)
- *   d_stats     optional [8] uint64 device counters: [0] filter fires (wave
- *               steps with a lane passing the fast filter), [1] lanes passing
- *               every ridge check, [2] vectors rejected by the upper bound
+ *   d_stats     optional [8] uint64 device counters: [0] candidates (vectors
+ *               passing the fast filter), [1] vectors passing every ridge
+ *               check, [2] vectors rejected by the upper bound, [3] wave
+ *               passes over the queued candidates
  * Asynchronous: returns after enqueueing.  Items must describe chunks inside
  * each instance's 2^max(k,7) Gray range (checked on the host for PLAIN mode
  * and by wpm_build_queue's construction otherwise).

@@ -145,8 +145,7 @@ int persistent_grid(const wpm_batch *b, int wg_size, int32_t *grid) {
     if (b->max_groups < 1 || b->max_groups > WPM_MAX_GROUPS) return WPM_EINVAL;
     if (b->max_slots != 4 && b->max_slots != 8) return WPM_EINVAL;
     const int gm = pick_gm(b->max_groups), qs = b->max_slots, wm = pick_wm(b->max_words);
-    const size_t lds =
-        (size_t)(WPM_TABLE_ROWS + b->max_kp + 2) * (size_t)b->max_row_words * sizeof(uint32_t);
+    const size_t lds = sweep_lds_bytes(b->max_kp, b->max_row_words, wg_size);
     int32_t cus = 0;
     int rc = device_query(&cus, nullptr, nullptr);
     if (rc) return rc;
@@ -185,8 +184,7 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     if (s->mode == WPM_SCHED_DYNAMIC && !s->d_scratch) return WPM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const int gm = pick_gm(b->max_groups), qs = b->max_slots, wm = pick_wm(b->max_words);
-    const size_t lds =
-        (size_t)(WPM_TABLE_ROWS + b->max_kp + 2) * (size_t)b->max_row_words * sizeof(uint32_t);
+    const size_t lds = sweep_lds_bytes(b->max_kp, b->max_row_words, s->wg_size);
     int32_t lds_max = 0;
     if (cap >= (UINT64_MAX >> 2)) return WPM_EINVAL;
     int rc = device_query(nullptr, nullptr, &lds_max);

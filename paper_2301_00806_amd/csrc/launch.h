@@ -1,6 +1,6 @@
 // Launch entry points of the kernel instantiations (one translation unit per
 // maximum group count GM in {2, 4, 8, 16}; slot stride QS in {4, 8}; facet
-// words WM in {4, 16, 32}).
+// words WM in {4, 10, 16, 32}).
 #pragma once
 #include <hip/hip_runtime.h>
 

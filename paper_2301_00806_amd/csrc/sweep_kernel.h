@@ -10,23 +10,30 @@
 //
 // A step checks the ridges whose parents Proposition 2.1 constrains, in the
 // bit-sliced slot form built by the packer (a ridge fails iff at least 3 of
-// its first p-1 parent bits are set).  Work is split in two phases per block
-// of 64 steps:
+// its first p-1 parent bits are set).  Work per block of 64 steps:
 //   phase 1  the fast filter: 32 ridges in 4 slot words held in VGPRs,
 //            updated by 4 XORs and tested by 2 bit-logic ops per step, the
-//            two halves of the block as interleaved chains; the steps where
-//            some lane passes are recorded in a 64-bit mask.
-//   phase 2  for each recorded step only: the lane's state is rebuilt as
-//            P ^ U[v], where P (per lane, VGPRs) is the contribution of the
-//            basis vectors above bit 6 and U (LDS, 64 rows staged per
-//            instance) the contribution of the low 6 bits v of x; the
-//            remaining ridge groups are checked with wave-uniform early exit,
-//            then the facet count |K| (the upper-bound property of Section
-//            4.2), further affine properties g(K) > 0 (Section 2.1) and
-//            x != 0 (x = 0 is allowed when the instance is an affine coset
-//            K* + span, whose offset row is added to every state).  Survivors are compacted with a wave ballot and
-//            prefix count into per-wave chunks of record slots (one global
-//            atomic per chunk); per-instance counts are flushed once per item.
+//            two halves of the block as interleaved chains.  Steps where a
+//            lane passes set that lane's bit in a 64-bit mask (a rarely
+//            taken branch).
+//   queue    each lane appends its passing steps to its own short queue in
+//            LDS (12-bit step numbers).
+//   check    when a queue is full, at the end of a 4096-step segment and at
+//            the end of the item, every lane takes its queued steps one at a
+//            time, all lanes in parallel: the full state at step r of the
+//            lane's chunk is P ^ S(gray(r)), with P (VGPRs) the state at the
+//            segment start and S(gray(r)) the XOR of four 8-row LDS tables
+//            indexed by the Gray bits 0-2, 3-5, 6-8 and 9-11.  The remaining
+//            ridge groups are checked with wave-uniform early exit, then the
+//            facet count |K| (the upper-bound property of Section 4.2),
+//            further affine properties g(K) > 0 (Section 2.1) and x != 0
+//            (x = 0 is allowed when the instance is an affine coset
+//            K* + span, whose offset row is added to every state).
+//            Survivors are compacted with a wave ballot and prefix count
+//            into per-wave chunks of record slots (one global atomic per
+//            chunk); per-instance counts are flushed once per item.
+// P therefore changes only when a step flips a basis vector t >= 12, once
+// per 4096 steps; phase 1 updates its 4 words at every block boundary.
 // Dot products and parities reduce to AND, XOR and popcount on bit masks, as
 // in Section 2.3.
 #pragma once
@@ -138,23 +145,31 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Occupancy: up to 8 ridge groups and 10 facet words (the bulk of the
-// Picard-number-4 instances with n <= 8) are compiled for 7 waves per SIMD
-// (at most 72 VGPRs); the few spills that costs sit in the per-item set-up and
-// the block boundary, not in the 64-step loop.  Measured on the 16384-instance
-// batch: 5, 6, 7 and 8 waves gave 205.8, 191.1, 180.4 and 187.3 ms.  Larger
-// templates keep the compiler's own register budget.
+// LDS of one workgroup: the per-lane queues and phase-1 save area, then the
+// tables of the staged instance (RS words per row): 4 x 8 rows for the Gray
+// bits 0-2, 3-5, 6-8 and 9-11, the kp basis rows plus the offset row, and the
+// reference state of the current item.
+constexpr int QCAP = 8;  // queued steps per lane
+__host__ __device__ constexpr size_t sweep_lds_bytes(int max_kp, int max_row_words, int wg_size) {
+    return (size_t)wg_size * (QCAP * sizeof(uint16_t) + 4 * sizeof(uint32_t)) +
+           (size_t)(WPM_TABLE_ROWS + max_kp + 2) * (size_t)max_row_words * sizeof(uint32_t);
+}
+
+// Occupancy: every instantiation is compiled for WPM_SWEEP_WAVES waves per
+// SIMD.  The hot state (the two phase-1 chains, the pass masks, the queue
+// length) needs few VGPRs; the words of P that do not fit are spilled, and P
+// is only read by the queue checks and written once per 4096 steps.
+#ifndef WPM_SWEEP_WAVES
+#define WPM_SWEEP_WAVES 7
+#endif
 template <int GM, int QS, int WM>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((WM <= 10 && GM <= 8) ? 7 : 1)))
-void sweep_kernel(const uint32_t *__restrict__ tables,
-                                                     const int64_t *__restrict__ offsets,
-                                                     const wpm_item *__restrict__ items, KArgs a_in) {
-    // LDS: [64][RS] U table (state contribution of every 6-bit low vector),
-    // then [kp][RS] basis rows of the staged instance.
-    extern __shared__ uint32_t lds_U[];
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPM_SWEEP_WAVES)))
+void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict__ offsets,
+                  const wpm_item *__restrict__ items, KArgs a_in) {
+    extern __shared__ uint32_t lds_dyn[];
     __shared__ unsigned long long s_item;
-    // The launch arguments live in LDS: phase 2 reads them there, which keeps
-    // them out of the scalar registers the fast loop needs.
+    // The launch arguments live in LDS: the check reads them there, which
+    // keeps them out of the scalar registers the fast loop needs.
     __shared__ KArgs s_a;
     if (threadIdx.x == 0) s_a = a_in;
     __syncthreads();
@@ -163,10 +178,13 @@ void sweep_kernel(const uint32_t *__restrict__ tables,
     constexpr int PW = Layout<GM, QS, WM>::PW;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    const int bd = blockDim.x;
+    uint16_t *lds_Q = reinterpret_cast<uint16_t *>(lds_dyn);  // [QCAP][bd] queued steps
+    uint32_t *lds_S = lds_dyn + QCAP * bd / 2;                  // [4][bd] phase-1 words
+    uint32_t *lds_L = lds_S + 4 * bd;                           // [32][RS] Gray-bit tables
     int64_t staged = -1;
-    // statistics, kept by lane 0 of each wave in VGPRs (SGPRs are the scarce
-    // resource of the fast loop)
-    uint32_t n_fire = 0, n_ridge = 0, n_ubt = 0;
+    // statistics of this wave (wave-uniform)
+    uint32_t n_cand = 0, n_ridge = 0, n_ubt = 0, n_pass = 0;
     // per-wave output chunk [out_pos, out_end) of record slots, and the
     // results found since the last flush
     uint64_t out_pos = 0, out_end = 0, wave_total = 0;
@@ -204,18 +222,19 @@ void sweep_kernel(const uint32_t *__restrict__ tables,
         const bool has_off = (tab[D_FLAGS] & D_FLAG_OFFSET) != 0u;
         const uint32_t *__restrict__ rows = tab + DEV_HDR_WORDS;
 
-        uint32_t *lds_R = lds_U + WPM_TABLE_ROWS * RS;  // [kp][RS] basis rows
+        uint32_t *lds_R = lds_L + WPM_TABLE_ROWS * RS;  // [kp + 1][RS] basis rows, offset
         if ((int64_t)inst != staged) {
-            for (int e = tid; e < (kp + (has_off ? 1 : 0)) * RS; e += blockDim.x) lds_R[e] = rows[e];
+            for (int e = tid; e < (kp + (has_off ? 1 : 0)) * RS; e += bd) lds_R[e] = rows[e];
             __syncthreads();
-            // U[v] = XOR of rows t over the set bits t of v (v < 64)
-            for (int e = tid; e < WPM_TABLE_ROWS * RS; e += blockDim.x) {
+            // table b, row v: XOR of the rows 3b + j over the set bits j of v
+            // (rows >= kp count as zero)
+            for (int e = tid; e < WPM_TABLE_ROWS * RS; e += bd) {
                 const int v = e / RS, w = e - v * RS;
+                const int t0 = 3 * (v >> 3);
                 uint32_t acc = 0;
-#pragma unroll
-                for (int t = 0; t < 6; ++t)
-                    if ((v >> t) & 1) acc ^= lds_R[t * RS + w];
-                lds_U[e] = acc;
+                for (int t = 0; t < 3; ++t)
+                    if (((v >> t) & 1) && t0 + t < kp) acc ^= lds_R[(t0 + t) * RS + w];
+                lds_L[e] = acc;
             }
             __syncthreads();
             staged = inst;
@@ -226,7 +245,7 @@ void sweep_kernel(const uint32_t *__restrict__ tables,
         uint32_t *lds_P = lds_R + (kp + 1) * RS;
         const uint64_t iref = first << c;
         const uint64_t xref = iref ^ (iref >> 1);
-        for (int w = tid; w < RS; w += blockDim.x) {
+        for (int w = tid; w < RS; w += bd) {
             uint32_t acc = has_off ? lds_R[kp * RS + w] : 0u;
             for (int t = 6; t < kp; ++t)
                 if ((xref >> t) & 1ull) acc ^= lds_R[t * RS + w];
@@ -261,6 +280,9 @@ void sweep_kernel(const uint32_t *__restrict__ tables,
 
             const uint64_t nblk = 1ull << (c - 6);
             const int koff = 4 + (G - 1) * mqs;
+            uint32_t qn = 0;          // steps in this lane's queue
+            uint32_t pa = 0, pb = 0;  // passing steps of the block: chain a, chain b
+            bool queued = false;      // wave-uniform: some lane's queue is not empty
             for (uint64_t blk = 0; blk < nblk; ++blk) {
                 // ---- phase 1: fast filter over 64 Gray steps, run as two
                 // interleaved chains: steps 0..31 from the block-start state
@@ -268,9 +290,8 @@ void sweep_kernel(const uint32_t *__restrict__ tables,
                 // bits of step 32 are bits 4 and 5).  Steps s and s + 32 flip
                 // the same basis vector, so both chains share the XOR operand;
                 // a step costs 7 VALU ops, and one rarely taken branch covers
-                // two steps.  The taken branch records each chain's step on
-                // its own, so phase 2 sees exactly the steps that passed.
-                uint64_t fire = 0;
+                // two steps and records each chain's passing lanes.
+                bool fired = false;  // wave-uniform: some lane passed in this block
                 uint32_t b0 = s0 ^ d[4][0] ^ d[5][0], b1 = s1 ^ d[4][1] ^ d[5][1];
                 uint32_t b2 = s2 ^ d[4][2] ^ d[5][2], b3 = s3 ^ d[4][3] ^ d[5][3];
 #pragma unroll
@@ -278,10 +299,10 @@ void sweep_kernel(const uint32_t *__restrict__ tables,
                     const uint32_t fa = fail4(s0, s1, s2, s3);
                     const uint32_t fb = fail4(b0, b1, b2, b3);
                     const uint32_t fm = fa < fb ? fa : fb;
-                    // inactive lanes may set a bit too; phase 2 masks them out
                     if (__builtin_expect(__builtin_amdgcn_ballot_w64(fm == 0u) != 0, 0)) {
-                        if (__builtin_amdgcn_ballot_w64(fa == 0u)) fire |= 1ull << s;
-                        if (__builtin_amdgcn_ballot_w64(fb == 0u)) fire |= 1ull << (s + 32);
+                        pa |= fa == 0u ? 1u << s : 0u;
+                        pb |= fb == 0u ? 1u << s : 0u;
+                        fired = true;
                     }
                     if (s < 31) {
                         const int t = __builtin_ctz((unsigned)(s + 1));
@@ -306,111 +327,175 @@ void sweep_kernel(const uint32_t *__restrict__ tables,
                 s1 = b1;
                 s2 = b2;
                 s3 = b3;
-                // ---- phase 2: exact check of the recorded steps
-                fire = rfl64(fire);  // wave-uniform: keep it in scalar registers
-                while (fire) {
-                    const int s = __builtin_ctzll(fire);
-                    fire &= fire - 1;
-                    if (lane == 0) ++n_fire;
-                    // low 6 bits of x at this step: Gray code of s, bit 5
-                    // toggled by the block parity
-                    const int v = (s ^ (s >> 1)) ^ ((int)(blk & 1ull) << 5);
-                    const uint32_t *T = lds_U + v * RS;
-                    bool pass = active && fail4(P[0] ^ T[0], P[1] ^ T[1], P[2] ^ T[2], P[3] ^ T[3]) == 0u;
-                    // groups in decreasing rejection order; stop once no lane passes
-                    int Gp = G, Qp = mqs;
-                    asm volatile("" : "+s"(Gp), "+s"(Qp));
-                    bool go = true;
-#pragma unroll
-                    for (int g = 1; g < GM; ++g) {
-                        go = go && g < Gp && __builtin_amdgcn_ballot_w64(pass) != 0;
-                        if (go) {
-                            uint32_t st[QS];
-#pragma unroll
-                            for (int q = 0; q < QS; ++q)
-                                st[q] = (QS == 4 || q < Qp)
-                                            ? P[4 + (g - 1) * QS + q] ^ T[4 + (g - 1) * Qp + q]
-                                            : 0u;
-                            pass = pass && fail_slots<QS>(st) == 0u;
+                // ---- queue this block's passing steps; check the queues when
+                // one is full, before P changes and at the end of the item.
+                // Blocks where no lane passed and no check is due skip all of
+                // it on a scalar test.
+                const bool seg_end = blk + 1 == nblk || ((blk + 1) & 63ull) == 0;
+                if (fired || (seg_end && queued)) {
+                if (!active) pa = pb = 0;
+                for (;;) {
+                    uint64_t app;
+                    while ((app = __builtin_amdgcn_ballot_w64((pa | pb) != 0u && qn < (uint32_t)QCAP)) != 0) {
+                        n_cand += (uint32_t)__builtin_popcountll(app);
+                        if ((pa | pb) != 0u && qn < (uint32_t)QCAP) {
+                            uint32_t s;
+                            if (pa) {
+                                s = __builtin_ctz(pa);
+                                pa &= pa - 1;
+                            } else {
+                                s = 32 + __builtin_ctz(pb);
+                                pb &= pb - 1;
+                            }
+                            lds_Q[qn * bd + tid] = (uint16_t)(((uint32_t)(blk & 63ull) << 6) | s);
+                            ++qn;
                         }
                     }
-                    const uint64_t i = i0 + (blk << 6) + (uint64_t)s;
-                    const uint64_t x = i ^ (i >> 1);
-                    // x = 0 is the empty complex, except in a coset (K = K*)
-                    pass = pass && (x != 0 || has_off) && (k >= 64 || (x >> k) == 0);
-                    if (__builtin_amdgcn_ballot_w64(pass)) {
-                        int Wp = W, ko = koff;
-                        asm volatile("" : "+s"(Wp), "+s"(ko));
-                        uint32_t cnt = 0;
+                    const bool more = __builtin_amdgcn_ballot_w64((pa | pb) != 0u) != 0;
+                    queued = __builtin_amdgcn_ballot_w64(qn != 0u) != 0;
+                    if (!more && !(seg_end && queued)) break;
+                    // the phase-1 words wait in LDS while the queues are
+                    // checked (the barrier keeps them out of VGPRs meanwhile)
+                    lds_S[tid] = s0;
+                    lds_S[bd + tid] = s1;
+                    lds_S[2 * bd + tid] = s2;
+                    lds_S[3 * bd + tid] = s3;
+                    asm volatile("" ::: "memory");
+                    // ---- check: every lane takes its queued steps in order
+                    // (the Gray index of the segment start has bit 12 =
+                    // segment parity, which toggles Gray bit 11)
+                    const uint64_t sbase = (blk >> 6) << 12;
+                    const uint32_t par = (uint32_t)((blk >> 6) & 1ull) << 11;
+                    for (uint32_t jq = 0; __builtin_amdgcn_ballot_w64(jq < qn) != 0; ++jq) {
+                        const bool has = jq < qn;
+                        ++n_pass;
+                        const uint32_t r12 = has ? (uint32_t)lds_Q[jq * bd + tid] : 0u;
+                        const uint32_t g12 = (r12 ^ (r12 >> 1)) ^ par;
+                        const uint32_t *T0 = lds_L + (g12 & 7u) * RS;
+                        const uint32_t *T1 = lds_L + (8u + ((g12 >> 3) & 7u)) * RS;
+                        const uint32_t *T2 = lds_L + (16u + ((g12 >> 6) & 7u)) * RS;
+                        const uint32_t *T3 = lds_L + (24u + (g12 >> 9)) * RS;
+                        // word of the state at this step: P ^ T0 ^ T1 ^ T2 ^ T3
+                        auto word = [&](int pi, int off) {
+                            return __builtin_amdgcn_bitop3_b32(
+                                __builtin_amdgcn_bitop3_b32(P[pi], T0[off], T1[off], 0x96), T2[off], T3[off], 0x96);
+                        };
+                        // group 0 passed in phase 1; the other groups in
+                        // decreasing rejection order, stopping once no lane passes
+                        bool pass = has;
+                        int Gp = G, Qp = mqs;
+                        asm volatile("" : "+s"(Gp), "+s"(Qp));
+                        bool go = true;
 #pragma unroll
-                        for (int w = 0; w < WM; ++w)
-                            if (w < Wp) cnt += __builtin_popcount(P[KR + w] ^ T[ko + w]);
-                        bool ok = pass && (maxf == 0u || cnt <= maxf);
-                        // further affine properties g(K) = c0 + sum_c w_c |K & mask_c| > 0
-                        const uint32_t np = tab[D_NPROPS];
-                        if (np != 0u && __builtin_amdgcn_ballot_w64(ok) != 0) {
-                            const uint32_t *pr = tab + tab[D_PROPS];
-                            for (uint32_t q = 0; q < np; ++q) {
-                                int64_t g = (int32_t)pr[0];
-                                const uint32_t ncls = pr[1];
-                                pr += 2;
-                                for (uint32_t cl = 0; cl < ncls; ++cl) {
-                                    uint32_t sum = 0;
+                        for (int g = 1; g < GM; ++g) {
+                            go = go && g < Gp && __builtin_amdgcn_ballot_w64(pass) != 0;
+                            if (go) {
+                                uint32_t st[QS];
 #pragma unroll
-                                    for (int w = 0; w < WM; ++w)
-                                        if (w < Wp) sum += __builtin_popcount((P[KR + w] ^ T[ko + w]) & pr[1 + w]);
-                                    g += (int64_t)(int32_t)pr[0] * (int64_t)sum;
-                                    pr += 1 + Wp;
-                                }
-                                ok = ok && g > 0;
+                                for (int q = 0; q < QS; ++q)
+                                    st[q] = (QS == 4 || q < Qp) ? word(4 + (g - 1) * QS + q, 4 + (g - 1) * Qp + q)
+                                                                : 0u;
+                                pass = pass && fail_slots<QS>(st) == 0u;
                             }
                         }
-                        const uint64_t pball = __builtin_amdgcn_ballot_w64(pass);
-                        const uint64_t bal = __builtin_amdgcn_ballot_w64(ok);
-                        if (lane == 0) {
+                        // Gray index: the lane's chunk start (recomputed: it
+                        // would otherwise hold two VGPRs through phase 1)
+                        uint64_t f0 = first;  // opaque: keeps the chunk start out of the block loop
+                        asm volatile("" : "+s"(f0));
+                        const uint64_t i = ((f0 + (uint64_t)tid) << c) + sbase + (uint64_t)r12;
+                        const uint64_t x = i ^ (i >> 1);
+                        // x = 0 is the empty complex, except in a coset (K = K*)
+                        pass = pass && (x != 0 || has_off) && (k >= 64 || (x >> k) == 0);
+                        if (__builtin_amdgcn_ballot_w64(pass)) {
+                            int Wp = W, ko = koff;
+                            asm volatile("" : "+s"(Wp), "+s"(ko));
+                            // one word at a time: issuing every word's three
+                            // table reads at once would need 3 * WM VGPRs
+                            uint32_t cnt = 0;
+#pragma unroll
+                            for (int w = 0; w < WM; ++w) {
+                                if (w < Wp) cnt += __builtin_popcount(word(KR + w, ko + w));
+                                asm volatile("" : "+v"(cnt)::"memory");
+                            }
+                            bool ok = pass && (maxf == 0u || cnt <= maxf);
+                            // further affine properties g(K) = c0 + sum_c w_c |K & mask_c| > 0
+                            const uint32_t np = tab[D_NPROPS];
+                            if (np != 0u && __builtin_amdgcn_ballot_w64(ok) != 0) {
+                                const uint32_t *pr = tab + tab[D_PROPS];
+                                for (uint32_t q = 0; q < np; ++q) {
+                                    int64_t gv = (int32_t)pr[0];
+                                    const uint32_t ncls = pr[1];
+                                    pr += 2;
+                                    for (uint32_t cl = 0; cl < ncls; ++cl) {
+                                        uint32_t sum = 0;
+#pragma unroll
+                                        for (int w = 0; w < WM; ++w) {
+                                            if (w < Wp) sum += __builtin_popcount(word(KR + w, ko + w) & pr[1 + w]);
+                                            asm volatile("" : "+v"(sum)::"memory");
+                                        }
+                                        gv += (int64_t)(int32_t)pr[0] * (int64_t)sum;
+                                        pr += 1 + Wp;
+                                    }
+                                    ok = ok && gv > 0;
+                                }
+                            }
+                            const uint64_t pball = __builtin_amdgcn_ballot_w64(pass);
+                            const uint64_t bal = __builtin_amdgcn_ballot_w64(ok);
                             n_ridge += (uint32_t)__builtin_popcountll(pball);
                             n_ubt += (uint32_t)__builtin_popcountll(pball & ~bal);
-                        }
-                        if (bal) {
-                            const uint32_t nb = (uint32_t)__builtin_popcountll(bal);
-                            item_cnt += nb;
-                            if (out_pos + nb > out_end) {
-                                // close the current chunk with sentinel
-                                // records and reserve a new one (one global
-                                // atomic per a.chunk record slots)
-                                for (uint64_t e0 = out_pos + (uint64_t)lane; e0 < out_end && e0 < a.cap;
-                                     e0 += 64) {
-                                    a.surv[2 * e0] = 0;
-                                    a.surv[2 * e0 + 1] = ~0ull;
+                            if (bal) {
+                                const uint32_t nb = (uint32_t)__builtin_popcountll(bal);
+                                item_cnt += nb;
+                                if (out_pos + nb > out_end) {
+                                    // close the current chunk with sentinel
+                                    // records and reserve a new one (one global
+                                    // atomic per a.chunk record slots)
+                                    for (uint64_t e0 = out_pos + (uint64_t)lane; e0 < out_end && e0 < a.cap;
+                                         e0 += 64) {
+                                        a.surv[2 * e0] = 0;
+                                        a.surv[2 * e0 + 1] = ~0ull;
+                                    }
+                                    const uint64_t want = a.chunk > nb ? a.chunk : nb;
+                                    unsigned long long base = 0;
+                                    if (lane == 0) base = atomicAdd(a.slots, (unsigned long long)want);
+                                    out_pos = rfl64(base);
+                                    out_end = out_pos + want;
                                 }
-                                const uint64_t want = a.chunk > nb ? a.chunk : nb;
-                                unsigned long long base = 0;
-                                if (lane == 0) base = atomicAdd(a.slots, (unsigned long long)want);
-                                out_pos = rfl64(base);
-                                out_end = out_pos + want;
-                            }
-                            if (ok) {
-                                const uint32_t rk = __builtin_amdgcn_mbcnt_hi(
-                                    (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                                const uint64_t pos = out_pos + rk;
-                                if (pos < a.cap) {
-                                    a.surv[2 * pos] = x;
-                                    a.surv[2 * pos + 1] = inst;
+                                if (ok) {
+                                    const uint32_t rk = __builtin_amdgcn_mbcnt_hi(
+                                        (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                                    const uint64_t pos = out_pos + rk;
+                                    if (pos < a.cap) {
+                                        a.surv[2 * pos] = x;
+                                        a.surv[2 * pos + 1] = inst;
+                                    }
                                 }
+                                out_pos += nb;
                             }
-                            out_pos += nb;
                         }
                     }
+                    qn = 0;
+                    queued = false;
+                    asm volatile("" ::: "memory");
+                    s0 = lds_S[tid];
+                    s1 = lds_S[bd + tid];
+                    s2 = lds_S[2 * bd + tid];
+                    s3 = lds_S[3 * bd + tid];
+                    if (!more) break;
                 }
-                // ---- block boundary: one more Gray step, flipping t >= 6
+                }
+                // ---- block boundary: one more Gray step, flipping t >= 6;
+                // P follows only the flips of t >= 12 (segment changes)
                 if (blk + 1 < nblk) {
-                    // opaque copy: keeps the per-group tests from being hoisted
-                    // out of the block loop as live lane masks
-                    int Gb = G, Wb = W, Qb = mqs;
-                    asm volatile("" : "+s"(Gb), "+s"(Wb), "+s"(Qb));
                     const int t = 6 + __builtin_ctzll(blk + 1);
                     const uint32_t *row = lds_R + t * RS;
-                    xor_row<GM, QS, WM>(P, row, ~0u, Gb, Wb, Qb);
+                    if (t >= 12) {
+                        // opaque copy: keeps the per-group tests from being
+                        // hoisted out of the block loop as live lane masks
+                        int Gb = G, Wb = W, Qb = mqs;
+                        asm volatile("" : "+s"(Gb), "+s"(Wb), "+s"(Qb));
+                        xor_row<GM, QS, WM>(P, row, ~0u, Gb, Wb, Qb);
+                    }
                     s0 ^= row[0];
                     s1 ^= row[1];
                     s2 ^= row[2];
@@ -432,10 +517,11 @@ void sweep_kernel(const uint32_t *__restrict__ tables,
         a.surv[2 * e0 + 1] = ~0ull;
     }
     if (lane == 0 && wave_total) atomicAdd(a.total, (unsigned long long)wave_total);
-    if (a.stats && lane == 0 && (n_fire | n_ridge | n_ubt)) {
-        atomicAdd(a.stats + 0, (unsigned long long)n_fire);
+    if (a.stats && lane == 0 && (n_cand | n_ridge | n_ubt | n_pass)) {
+        atomicAdd(a.stats + 0, (unsigned long long)n_cand);
         atomicAdd(a.stats + 1, (unsigned long long)n_ridge);
         atomicAdd(a.stats + 2, (unsigned long long)n_ubt);
+        atomicAdd(a.stats + 3, (unsigned long long)n_pass);
     }
 }
 
