@@ -13,25 +13,25 @@
 // its first p-1 parent bits are set).  Work per block of 64 steps:
 //   phase 1  the fast filter: 32 ridges in 4 slot words held in VGPRs,
 //            updated by 4 XORs and tested by 2 bit-logic ops per step, the
-//            two halves of the block as interleaved chains.  Steps where a
-//            lane passes set that lane's bit in a 64-bit mask (a rarely
-//            taken branch).
-//   queue    each lane appends its passing steps to its own short queue in
-//            LDS (12-bit step numbers).
-//   check    when a queue is full, at the end of a 4096-step segment and at
-//            the end of the item, every lane takes its queued steps one at a
-//            time, all lanes in parallel: the full state at step r of the
-//            lane's chunk is P ^ S(gray(r)), with P (VGPRs) the state at the
-//            segment start and S(gray(r)) the XOR of four 8-row LDS tables
-//            indexed by the Gray bits 0-2, 3-5, 6-8 and 9-11.  The remaining
-//            ridge groups are checked with wave-uniform early exit, then the
-//            facet count |K| (the upper-bound property of Section 4.2),
-//            further affine properties g(K) > 0 (Section 2.1) and x != 0
-//            (x = 0 is allowed when the instance is an affine coset
-//            K* + span, whose offset row is added to every state).
-//            Survivors are compacted with a wave ballot and prefix count
-//            into per-wave chunks of record slots (one global atomic per
-//            chunk); per-instance counts are flushed once per item.
+//            two halves of the block as interleaved chains.  When a lane
+//            passes (a rarely taken branch), the passing lanes append
+//            (step, lane) to the wave's candidate list in LDS; ballot and
+//            mbcnt give the slots, the count is wave-uniform.
+//   check    when the list is half full, at the end of a 4096-step segment
+//            and at the end of the item, lane j of the wave takes entry j
+//            (64 entries per pass).  The full state of the owner lane at
+//            step r of its chunk is P ^ S(gray(r)): P (the owner's VGPRs,
+//            fetched with ds_bpermute) is the state at the segment start and
+//            S(gray(r)) the XOR of four 8-row LDS tables indexed by the Gray
+//            bits 0-2, 3-5, 6-8 and 9-11.  The remaining ridge groups are
+//            checked with wave-uniform early exit, then the facet count |K|
+//            (the upper-bound property of Section 4.2), further affine
+//            properties g(K) > 0 (Section 2.1) and x != 0 (x = 0 is allowed
+//            when the instance is an affine coset K* + span, whose offset
+//            row is added to every state).  Survivors are compacted with a
+//            wave ballot and prefix count into per-wave chunks of record
+//            slots (one global atomic per chunk); per-instance counts are
+//            flushed once per item.
 // P therefore changes only when a step flips a basis vector t >= 12, once
 // per 4096 steps; phase 1 updates its 4 words at every block boundary.
 // Dot products and parities reduce to AND, XOR and popcount on bit masks, as
@@ -145,20 +145,21 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// LDS of one workgroup: the per-lane queues and phase-1 save area, then the
-// tables of the staged instance (RS words per row): 4 x 8 rows for the Gray
-// bits 0-2, 3-5, 6-8 and 9-11, the kp basis rows plus the offset row, and the
-// reference state of the current item.
-constexpr int QCAP = 8;  // queued steps per lane
+// LDS of one workgroup: a candidate list per wave and the phase-1 save area,
+// then the tables of the staged instance (RS words per row): 4 x 8 rows for
+// the Gray bits 0-2, 3-5, 6-8 and 9-11, the kp basis rows plus the offset row,
+// and the reference state of the current item.
+constexpr int LIST_CAP = 256;   // candidates a wave's list holds
+constexpr int LIST_FLUSH = 128; // a block ending with at least this many checks them
 __host__ __device__ constexpr size_t sweep_lds_bytes(int max_kp, int max_row_words, int wg_size) {
-    return (size_t)wg_size * (QCAP * sizeof(uint16_t) + 4 * sizeof(uint32_t)) +
+    return (size_t)wg_size * (LIST_CAP / 64 + 4) * sizeof(uint32_t) +
            (size_t)(WPM_TABLE_ROWS + max_kp + 2) * (size_t)max_row_words * sizeof(uint32_t);
 }
 
 // Occupancy: every instantiation is compiled for WPM_SWEEP_WAVES waves per
-// SIMD.  The hot state (the two phase-1 chains, the pass masks, the queue
-// length) needs few VGPRs; the words of P that do not fit are spilled, and P
-// is only read by the queue checks and written once per 4096 steps.
+// SIMD.  The hot state (the two phase-1 chains) needs few VGPRs; the words of
+// P that do not fit are spilled, and P is only read by the list checks and
+// written once per 4096 steps.
 #ifndef WPM_SWEEP_WAVES
 #define WPM_SWEEP_WAVES 7
 #endif
@@ -179,12 +180,13 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int bd = blockDim.x;
-    uint16_t *lds_Q = reinterpret_cast<uint16_t *>(lds_dyn);  // [QCAP][bd] queued steps
-    uint32_t *lds_S = lds_dyn + QCAP * bd / 2;                  // [4][bd] phase-1 words
-    uint32_t *lds_L = lds_S + 4 * bd;                           // [32][RS] Gray-bit tables
+    uint32_t *lds_S = lds_dyn + (bd / 64) * LIST_CAP;  // [4][bd] phase-1 words
+    uint32_t *lds_L = lds_S + 4 * bd;                  // [32][RS] Gray-bit tables
     int64_t staged = -1;
     // statistics of this wave (wave-uniform)
     uint32_t n_cand = 0, n_ridge = 0, n_ubt = 0, n_pass = 0;
+    // this wave's candidate list: entries (step r12 << 6) | lane
+    uint32_t *lds_W = lds_dyn + (tid >> 6) * LIST_CAP;
     // per-wave output chunk [out_pos, out_end) of record slots, and the
     // results found since the last flush
     uint64_t out_pos = 0, out_end = 0, wave_total = 0;
@@ -280,9 +282,8 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
 
             const uint64_t nblk = 1ull << (c - 6);
             const int koff = 4 + (G - 1) * mqs;
-            uint32_t qn = 0;          // steps in this lane's queue
-            uint32_t pa = 0, pb = 0;  // passing steps of the block: chain a, chain b
-            bool queued = false;      // wave-uniform: some lane's queue is not empty
+            const int wbase = tid & ~63;
+            uint32_t cnt = 0;  // wave-uniform: entries in the list
             for (uint64_t blk = 0; blk < nblk; ++blk) {
                 // ---- phase 1: fast filter over 64 Gray steps, run as two
                 // interleaved chains: steps 0..31 from the block-start state
@@ -290,8 +291,10 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                 // bits of step 32 are bits 4 and 5).  Steps s and s + 32 flip
                 // the same basis vector, so both chains share the XOR operand;
                 // a step costs 7 VALU ops, and one rarely taken branch covers
-                // two steps and records each chain's passing lanes.
-                bool fired = false;  // wave-uniform: some lane passed in this block
+                // two steps and appends the passing lanes to the wave's list
+                // (ballot + mbcnt give the slots).  Steps that would overflow
+                // the list are only marked in a scalar mask and rechecked below.
+                uint64_t redo = 0;
                 uint32_t b0 = s0 ^ d[4][0] ^ d[5][0], b1 = s1 ^ d[4][1] ^ d[5][1];
                 uint32_t b2 = s2 ^ d[4][2] ^ d[5][2], b3 = s3 ^ d[4][3] ^ d[5][3];
 #pragma unroll
@@ -300,9 +303,24 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                     const uint32_t fb = fail4(b0, b1, b2, b3);
                     const uint32_t fm = fa < fb ? fa : fb;
                     if (__builtin_expect(__builtin_amdgcn_ballot_w64(fm == 0u) != 0, 0)) {
-                        pa |= fa == 0u ? 1u << s : 0u;
-                        pb |= fb == 0u ? 1u << s : 0u;
-                        fired = true;
+                        const uint64_t ba = __builtin_amdgcn_ballot_w64(fa == 0u);
+                        const uint64_t bb = __builtin_amdgcn_ballot_w64(fb == 0u);
+                        const uint32_t na = (uint32_t)__builtin_popcountll(ba);
+                        const uint32_t nb = (uint32_t)__builtin_popcountll(bb);
+                        if (cnt + na + nb <= (uint32_t)LIST_CAP) {
+                            const uint32_t ln = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+                            const uint32_t e = ((((uint32_t)blk & 63u) << 6 | (uint32_t)s) << 6) | ln;
+                            if (fa == 0u)
+                                lds_W[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(ba >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)ba, 0u))] = e;
+                            if (fb == 0u)
+                                lds_W[cnt + na + __builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32),
+                                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0u))] =
+                                    e + (32u << 6);
+                            cnt += na + nb;
+                        } else {
+                            redo |= (ba ? 1ull << s : 0ull) | (bb ? 1ull << (s + 32) : 0ull);
+                        }
                     }
                     if (s < 31) {
                         const int t = __builtin_ctz((unsigned)(s + 1));
@@ -327,162 +345,175 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                 s1 = b1;
                 s2 = b2;
                 s3 = b3;
-                // ---- queue this block's passing steps; check the queues when
-                // one is full, before P changes and at the end of the item.
-                // Blocks where no lane passed and no check is due skip all of
-                // it on a scalar test.
+                // ---- check the list when it is half full, before P changes
+                // and at the end of the item; list the overflow steps first.
+                // Blocks with nothing to do skip all of it on a scalar test.
                 const bool seg_end = blk + 1 == nblk || ((blk + 1) & 63ull) == 0;
-                if (fired || (seg_end && queued)) {
-                if (!active) pa = pb = 0;
-                for (;;) {
-                    uint64_t app;
-                    while ((app = __builtin_amdgcn_ballot_w64((pa | pb) != 0u && qn < (uint32_t)QCAP)) != 0) {
-                        n_cand += (uint32_t)__builtin_popcountll(app);
-                        if ((pa | pb) != 0u && qn < (uint32_t)QCAP) {
-                            uint32_t s;
-                            if (pa) {
-                                s = __builtin_ctz(pa);
-                                pa &= pa - 1;
-                            } else {
-                                s = 32 + __builtin_ctz(pb);
-                                pb &= pb - 1;
-                            }
-                            lds_Q[qn * bd + tid] = (uint16_t)(((uint32_t)(blk & 63ull) << 6) | s);
-                            ++qn;
-                        }
-                    }
-                    const bool more = __builtin_amdgcn_ballot_w64((pa | pb) != 0u) != 0;
-                    queued = __builtin_amdgcn_ballot_w64(qn != 0u) != 0;
-                    if (!more && !(seg_end && queued)) break;
-                    // the phase-1 words wait in LDS while the queues are
-                    // checked (the barrier keeps them out of VGPRs meanwhile)
+                if (redo != 0 || cnt >= (uint32_t)LIST_FLUSH || (seg_end && cnt != 0)) {
+                    // the phase-1 words wait in LDS meanwhile (the barrier
+                    // keeps them out of VGPRs)
                     lds_S[tid] = s0;
                     lds_S[bd + tid] = s1;
                     lds_S[2 * bd + tid] = s2;
                     lds_S[3 * bd + tid] = s3;
                     asm volatile("" ::: "memory");
-                    // ---- check: every lane takes its queued steps in order
-                    // (the Gray index of the segment start has bit 12 =
-                    // segment parity, which toggles Gray bit 11)
+                    // state words at step r12 of the segment: P ^ the four
+                    // table rows of its Gray bits (bit 12 of the Gray index,
+                    // the segment parity, toggles Gray bit 11)
                     const uint64_t sbase = (blk >> 6) << 12;
                     const uint32_t par = (uint32_t)((blk >> 6) & 1ull) << 11;
-                    for (uint32_t jq = 0; __builtin_amdgcn_ballot_w64(jq < qn) != 0; ++jq) {
-                        const bool has = jq < qn;
-                        ++n_pass;
-                        const uint32_t r12 = has ? (uint32_t)lds_Q[jq * bd + tid] : 0u;
-                        const uint32_t g12 = (r12 ^ (r12 >> 1)) ^ par;
-                        const uint32_t *T0 = lds_L + (g12 & 7u) * RS;
-                        const uint32_t *T1 = lds_L + (8u + ((g12 >> 3) & 7u)) * RS;
-                        const uint32_t *T2 = lds_L + (16u + ((g12 >> 6) & 7u)) * RS;
-                        const uint32_t *T3 = lds_L + (24u + (g12 >> 9)) * RS;
-                        // word of the state at this step: P ^ T0 ^ T1 ^ T2 ^ T3
-                        auto word = [&](int pi, int off) {
-                            return __builtin_amdgcn_bitop3_b32(
-                                __builtin_amdgcn_bitop3_b32(P[pi], T0[off], T1[off], 0x96), T2[off], T3[off], 0x96);
-                        };
-                        // group 0 passed in phase 1; the other groups in
-                        // decreasing rejection order, stopping once no lane passes
-                        bool pass = has;
-                        int Gp = G, Qp = mqs;
-                        asm volatile("" : "+s"(Gp), "+s"(Qp));
-                        bool go = true;
+                    uint64_t rd = redo;
+                    for (;;) {
+                        // overflow steps: every lane rechecks the fast filter
+                        // on the rebuilt group-0 words; passing lanes are listed
+                        while (rd != 0 && cnt + 64u <= (uint32_t)LIST_CAP) {
+                            const uint32_t st = (uint32_t)__builtin_ctzll(rd);
+                            rd &= rd - 1;
+                            const uint32_t r12 = ((uint32_t)(blk & 63ull) << 6) | st;
+                            const uint32_t g12 = (r12 ^ (r12 >> 1)) ^ par;
+                            const uint32_t *T0 = lds_L + (g12 & 7u) * RS;
+                            const uint32_t *T1 = lds_L + (8u + ((g12 >> 3) & 7u)) * RS;
+                            const uint32_t *T2 = lds_L + (16u + ((g12 >> 6) & 7u)) * RS;
+                            const uint32_t *T3 = lds_L + (24u + (g12 >> 9)) * RS;
+                            uint32_t w4[4];
 #pragma unroll
-                        for (int g = 1; g < GM; ++g) {
-                            go = go && g < Gp && __builtin_amdgcn_ballot_w64(pass) != 0;
-                            if (go) {
-                                uint32_t st[QS];
-#pragma unroll
-                                for (int q = 0; q < QS; ++q)
-                                    st[q] = (QS == 4 || q < Qp) ? word(4 + (g - 1) * QS + q, 4 + (g - 1) * Qp + q)
-                                                                : 0u;
-                                pass = pass && fail_slots<QS>(st) == 0u;
-                            }
+                            for (int q = 0; q < 4; ++q)
+                                w4[q] = __builtin_amdgcn_bitop3_b32(
+                                    __builtin_amdgcn_bitop3_b32(P[q], T0[q], T1[q], 0x96), T2[q], T3[q], 0x96);
+                            const bool p0 = fail4(w4[0], w4[1], w4[2], w4[3]) == 0u;
+                            const uint64_t bp = __builtin_amdgcn_ballot_w64(p0);
+                            if (p0)
+                                lds_W[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(bp >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bp, 0u))] =
+                                    (r12 << 6) | (uint32_t)lane;
+                            cnt += (uint32_t)__builtin_popcountll(bp);
                         }
-                        // Gray index: the lane's chunk start (recomputed: it
-                        // would otherwise hold two VGPRs through phase 1)
-                        uint64_t f0 = first;  // opaque: keeps the chunk start out of the block loop
-                        asm volatile("" : "+s"(f0));
-                        const uint64_t i = ((f0 + (uint64_t)tid) << c) + sbase + (uint64_t)r12;
-                        const uint64_t x = i ^ (i >> 1);
-                        // x = 0 is the empty complex, except in a coset (K = K*)
-                        pass = pass && (x != 0 || has_off) && (k >= 64 || (x >> k) == 0);
-                        if (__builtin_amdgcn_ballot_w64(pass)) {
-                            int Wp = W, ko = koff;
-                            asm volatile("" : "+s"(Wp), "+s"(ko));
-                            // one word at a time: issuing every word's three
-                            // table reads at once would need 3 * WM VGPRs
-                            uint32_t cnt = 0;
+                        if (cnt >= (uint32_t)LIST_FLUSH || rd != 0 || seg_end) {
+                            n_cand += cnt;
+                            // ---- check: lane j takes entry base + j; the
+                            // owner's P words arrive by ds_bpermute
+                            for (uint32_t base = 0; base < cnt; base += 64) {
+                                ++n_pass;
+                                const uint32_t ent = base + (uint32_t)lane < cnt ? lds_W[base + lane] : 0u;
+                                const uint32_t own = ent & 63u, r12 = ent >> 6;
+                                const int src = (int)(own << 2);
+                                const uint32_t g12 = (r12 ^ (r12 >> 1)) ^ par;
+                                const uint32_t *T0 = lds_L + (g12 & 7u) * RS;
+                                const uint32_t *T1 = lds_L + (8u + ((g12 >> 3) & 7u)) * RS;
+                                const uint32_t *T2 = lds_L + (16u + ((g12 >> 6) & 7u)) * RS;
+                                const uint32_t *T3 = lds_L + (24u + (g12 >> 9)) * RS;
+                                // word of the listed state: owner's P ^ T0 ^ T1 ^ T2 ^ T3
+                                auto word = [&](int pi, int off) {
+                                    const uint32_t pw = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)P[pi]);
+                                    return __builtin_amdgcn_bitop3_b32(
+                                        __builtin_amdgcn_bitop3_b32(pw, T0[off], T1[off], 0x96), T2[off], T3[off], 0x96);
+                                };
+                                // group 0 passed in phase 1; the other groups in
+                                // decreasing rejection order, stopping once no
+                                // entry passes.  Entries of lanes beyond the
+                                // item's last chunk are dropped.
+                                bool pass = base + (uint32_t)lane < cnt && wbase + (int)own < lanes;
+                                int Gp = G, Qp = mqs;
+                                asm volatile("" : "+s"(Gp), "+s"(Qp));
+                                bool go = true;
 #pragma unroll
-                            for (int w = 0; w < WM; ++w) {
-                                if (w < Wp) cnt += __builtin_popcount(word(KR + w, ko + w));
-                                asm volatile("" : "+v"(cnt)::"memory");
-                            }
-                            bool ok = pass && (maxf == 0u || cnt <= maxf);
-                            // further affine properties g(K) = c0 + sum_c w_c |K & mask_c| > 0
-                            const uint32_t np = tab[D_NPROPS];
-                            if (np != 0u && __builtin_amdgcn_ballot_w64(ok) != 0) {
-                                const uint32_t *pr = tab + tab[D_PROPS];
-                                for (uint32_t q = 0; q < np; ++q) {
-                                    int64_t gv = (int32_t)pr[0];
-                                    const uint32_t ncls = pr[1];
-                                    pr += 2;
-                                    for (uint32_t cl = 0; cl < ncls; ++cl) {
-                                        uint32_t sum = 0;
+                                for (int g = 1; g < GM; ++g) {
+                                    go = go && g < Gp && __builtin_amdgcn_ballot_w64(pass) != 0;
+                                    if (go) {
+                                        uint32_t stw[QS];
 #pragma unroll
-                                        for (int w = 0; w < WM; ++w) {
-                                            if (w < Wp) sum += __builtin_popcount(word(KR + w, ko + w) & pr[1 + w]);
-                                            asm volatile("" : "+v"(sum)::"memory");
+                                        for (int q = 0; q < QS; ++q)
+                                            stw[q] = (QS == 4 || q < Qp)
+                                                         ? word(4 + (g - 1) * QS + q, 4 + (g - 1) * Qp + q)
+                                                         : 0u;
+                                        pass = pass && fail_slots<QS>(stw) == 0u;
+                                    }
+                                }
+                                // Gray index of the owner's step (the chunk
+                                // start is recomputed, not held through phase 1)
+                                uint64_t f0 = first;
+                                asm volatile("" : "+s"(f0));
+                                const uint64_t i = ((f0 + (uint64_t)(wbase + (int)own)) << c) + sbase + (uint64_t)r12;
+                                const uint64_t x = i ^ (i >> 1);
+                                // x = 0 is the empty complex, except in a coset (K = K*)
+                                pass = pass && (x != 0 || has_off) && (k >= 64 || (x >> k) == 0);
+                                if (__builtin_amdgcn_ballot_w64(pass)) {
+                                    int Wp = W, ko = koff;
+                                    asm volatile("" : "+s"(Wp), "+s"(ko));
+                                    // one word at a time: issuing every word's
+                                    // reads at once would need 5 * WM VGPRs
+                                    uint32_t cntf = 0;
+#pragma unroll
+                                    for (int w = 0; w < WM; ++w) {
+                                        if (w < Wp) cntf += __builtin_popcount(word(KR + w, ko + w));
+                                        asm volatile("" : "+v"(cntf)::"memory");
+                                    }
+                                    bool ok = pass && (maxf == 0u || cntf <= maxf);
+                                    // further affine properties g(K) = c0 + sum_c w_c |K & mask_c| > 0
+                                    const uint32_t np = tab[D_NPROPS];
+                                    if (np != 0u && __builtin_amdgcn_ballot_w64(ok) != 0) {
+                                        const uint32_t *pr = tab + tab[D_PROPS];
+                                        for (uint32_t q = 0; q < np; ++q) {
+                                            int64_t gv = (int32_t)pr[0];
+                                            const uint32_t ncls = pr[1];
+                                            pr += 2;
+                                            for (uint32_t cl = 0; cl < ncls; ++cl) {
+                                                uint32_t sum = 0;
+#pragma unroll
+                                                for (int w = 0; w < WM; ++w) {
+                                                    if (w < Wp) sum += __builtin_popcount(word(KR + w, ko + w) & pr[1 + w]);
+                                                    asm volatile("" : "+v"(sum)::"memory");
+                                                }
+                                                gv += (int64_t)(int32_t)pr[0] * (int64_t)sum;
+                                                pr += 1 + Wp;
+                                            }
+                                            ok = ok && gv > 0;
                                         }
-                                        gv += (int64_t)(int32_t)pr[0] * (int64_t)sum;
-                                        pr += 1 + Wp;
                                     }
-                                    ok = ok && gv > 0;
+                                    const uint64_t pball = __builtin_amdgcn_ballot_w64(pass);
+                                    const uint64_t bal = __builtin_amdgcn_ballot_w64(ok);
+                                    n_ridge += (uint32_t)__builtin_popcountll(pball);
+                                    n_ubt += (uint32_t)__builtin_popcountll(pball & ~bal);
+                                    if (bal) {
+                                        const uint32_t nbal = (uint32_t)__builtin_popcountll(bal);
+                                        item_cnt += nbal;
+                                        if (out_pos + nbal > out_end) {
+                                            // close the current chunk with sentinel
+                                            // records and reserve a new one (one
+                                            // global atomic per a.chunk record slots)
+                                            for (uint64_t e0 = out_pos + (uint64_t)lane; e0 < out_end && e0 < a.cap;
+                                                 e0 += 64) {
+                                                a.surv[2 * e0] = 0;
+                                                a.surv[2 * e0 + 1] = ~0ull;
+                                            }
+                                            const uint64_t want = a.chunk > nbal ? a.chunk : nbal;
+                                            unsigned long long rbase = 0;
+                                            if (lane == 0) rbase = atomicAdd(a.slots, (unsigned long long)want);
+                                            out_pos = rfl64(rbase);
+                                            out_end = out_pos + want;
+                                        }
+                                        if (ok) {
+                                            const uint32_t rk = __builtin_amdgcn_mbcnt_hi(
+                                                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                                            const uint64_t pos = out_pos + rk;
+                                            if (pos < a.cap) {
+                                                a.surv[2 * pos] = x;
+                                                a.surv[2 * pos + 1] = inst;
+                                            }
+                                        }
+                                        out_pos += nbal;
+                                    }
                                 }
                             }
-                            const uint64_t pball = __builtin_amdgcn_ballot_w64(pass);
-                            const uint64_t bal = __builtin_amdgcn_ballot_w64(ok);
-                            n_ridge += (uint32_t)__builtin_popcountll(pball);
-                            n_ubt += (uint32_t)__builtin_popcountll(pball & ~bal);
-                            if (bal) {
-                                const uint32_t nb = (uint32_t)__builtin_popcountll(bal);
-                                item_cnt += nb;
-                                if (out_pos + nb > out_end) {
-                                    // close the current chunk with sentinel
-                                    // records and reserve a new one (one global
-                                    // atomic per a.chunk record slots)
-                                    for (uint64_t e0 = out_pos + (uint64_t)lane; e0 < out_end && e0 < a.cap;
-                                         e0 += 64) {
-                                        a.surv[2 * e0] = 0;
-                                        a.surv[2 * e0 + 1] = ~0ull;
-                                    }
-                                    const uint64_t want = a.chunk > nb ? a.chunk : nb;
-                                    unsigned long long base = 0;
-                                    if (lane == 0) base = atomicAdd(a.slots, (unsigned long long)want);
-                                    out_pos = rfl64(base);
-                                    out_end = out_pos + want;
-                                }
-                                if (ok) {
-                                    const uint32_t rk = __builtin_amdgcn_mbcnt_hi(
-                                        (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                                    const uint64_t pos = out_pos + rk;
-                                    if (pos < a.cap) {
-                                        a.surv[2 * pos] = x;
-                                        a.surv[2 * pos + 1] = inst;
-                                    }
-                                }
-                                out_pos += nb;
-                            }
+                            cnt = 0;
                         }
+                        if (rd == 0) break;
                     }
-                    qn = 0;
-                    queued = false;
                     asm volatile("" ::: "memory");
                     s0 = lds_S[tid];
                     s1 = lds_S[bd + tid];
                     s2 = lds_S[2 * bd + tid];
                     s3 = lds_S[3 * bd + tid];
-                    if (!more) break;
-                }
                 }
                 // ---- block boundary: one more Gray step, flipping t >= 6;
                 // P follows only the flips of t >= 12 (segment changes)
