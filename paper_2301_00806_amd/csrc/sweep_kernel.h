@@ -183,13 +183,20 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
     uint32_t *lds_S = lds_dyn + (bd / 64) * LIST_CAP;  // [4][bd] phase-1 words
     uint32_t *lds_L = lds_S + 4 * bd;                  // [32][RS] Gray-bit tables
     int64_t staged = -1;
-    // statistics of this wave (wave-uniform)
-    uint32_t n_cand = 0, n_ridge = 0, n_ubt = 0, n_pass = 0;
+    // Per-wave bookkeeping, only touched by the checks: it lives in LDS, so
+    // that none of it holds scalar registers through phase 1 (the memory
+    // barriers of the check keep the compiler from caching it there).
+    // [out_pos, out_end) is the wave's current chunk of record slots.
+    struct Book {
+        uint64_t out_pos, out_end, wave_total;
+        uint32_t item_cnt, n_cand, n_ridge, n_ubt, n_pass, pad;
+    };
+    __shared__ Book s_book[512 / 64];
+    Book &bk = s_book[tid >> 6];
+    bk.out_pos = bk.out_end = bk.wave_total = 0;
+    bk.item_cnt = bk.n_cand = bk.n_ridge = bk.n_ubt = bk.n_pass = 0;
     // this wave's candidate list: entries (step r12 << 6) | lane
     uint32_t *lds_W = lds_dyn + (tid >> 6) * LIST_CAP;
-    // per-wave output chunk [out_pos, out_end) of record slots, and the
-    // results found since the last flush
-    uint64_t out_pos = 0, out_end = 0, wave_total = 0;
 
     for (int64_t round = 0;; ++round) {
         int64_t it;
@@ -255,7 +262,7 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
         }
         __syncthreads();
 
-        uint32_t item_cnt = 0;  // results of this item found by this wave
+        bk.item_cnt = 0;  // results of this item found by this wave
         // wave-uniform test (readfirstlane tells the compiler so)
         if ((int)__builtin_amdgcn_readfirstlane((uint32_t)(tid & ~63)) < lanes) {
             const bool active = tid < lanes;
@@ -284,6 +291,19 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
             const int koff = 4 + (G - 1) * mqs;
             const int wbase = tid & ~63;
             uint32_t cnt = 0;  // wave-uniform: entries in the list
+            // Header and item fields for the checks, re-read through an
+            // opaque pointer (scalar cache) rather than held in scalar
+            // registers through phase 1.
+            auto hv = [&](int i) -> uint32_t {
+                const uint32_t *tv = tab;
+                asm volatile("" : "+s"(tv));
+                return tv[i];
+            };
+            auto iv = [&]() -> wpm_item {
+                const wpm_item *ip = items + rfl64((uint64_t)it);
+                asm volatile("" : "+s"(ip));
+                return *ip;
+            };
             for (uint64_t blk = 0; blk < nblk; ++blk) {
                 // ---- phase 1: fast filter over 64 Gray steps, run as two
                 // interleaved chains: steps 0..31 from the block-start state
@@ -389,11 +409,11 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                             cnt += (uint32_t)__builtin_popcountll(bp);
                         }
                         if (cnt >= (uint32_t)LIST_FLUSH || rd != 0 || seg_end) {
-                            n_cand += cnt;
+                            bk.n_cand += cnt;
                             // ---- check: lane j takes entry base + j; the
                             // owner's P words arrive by ds_bpermute
                             for (uint32_t base = 0; base < cnt; base += 64) {
-                                ++n_pass;
+                                ++bk.n_pass;
                                 const uint32_t ent = base + (uint32_t)lane < cnt ? lds_W[base + lane] : 0u;
                                 const uint32_t own = ent & 63u, r12 = ent >> 6;
                                 const int src = (int)(own << 2);
@@ -412,9 +432,10 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                                 // decreasing rejection order, stopping once no
                                 // entry passes.  Entries of lanes beyond the
                                 // item's last chunk are dropped.
-                                bool pass = base + (uint32_t)lane < cnt && wbase + (int)own < lanes;
-                                int Gp = G, Qp = mqs;
-                                asm volatile("" : "+s"(Gp), "+s"(Qp));
+                                const wpm_item ci = iv();
+                                bool pass = base + (uint32_t)lane < cnt &&
+                                            wbase + (int)own < (int)__builtin_amdgcn_readfirstlane((uint32_t)ci.lanes);
+                                const int Gp = (int)hv(D_G), Qp = (QS == 4) ? 4 : (int)hv(D_QS);
                                 bool go = true;
 #pragma unroll
                                 for (int g = 1; g < GM; ++g) {
@@ -431,15 +452,16 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                                 }
                                 // Gray index of the owner's step (the chunk
                                 // start is recomputed, not held through phase 1)
-                                uint64_t f0 = first;
-                                asm volatile("" : "+s"(f0));
-                                const uint64_t i = ((f0 + (uint64_t)(wbase + (int)own)) << c) + sbase + (uint64_t)r12;
+                                const uint64_t f0 = rfl64(ci.first);
+                                const int cc = (int)__builtin_amdgcn_readfirstlane((uint32_t)ci.cbits);
+                                const uint64_t i = ((f0 + (uint64_t)(wbase + (int)own)) << cc) + sbase + (uint64_t)r12;
                                 const uint64_t x = i ^ (i >> 1);
                                 // x = 0 is the empty complex, except in a coset (K = K*)
-                                pass = pass && (x != 0 || has_off) && (k >= 64 || (x >> k) == 0);
+                                const int kk = (int)hv(D_K);
+                                const bool offs = (hv(D_FLAGS) & D_FLAG_OFFSET) != 0u;
+                                pass = pass && (x != 0 || offs) && (kk >= 64 || (x >> kk) == 0);
                                 if (__builtin_amdgcn_ballot_w64(pass)) {
-                                    int Wp = W, ko = koff;
-                                    asm volatile("" : "+s"(Wp), "+s"(ko));
+                                    const int Wp = (int)hv(D_W), ko = 4 + (Gp - 1) * Qp;
                                     // one word at a time: issuing every word's
                                     // reads at once would need 5 * WM VGPRs
                                     uint32_t cntf = 0;
@@ -448,11 +470,12 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                                         if (w < Wp) cntf += __builtin_popcount(word(KR + w, ko + w));
                                         asm volatile("" : "+v"(cntf)::"memory");
                                     }
-                                    bool ok = pass && (maxf == 0u || cntf <= maxf);
+                                    const uint32_t mf = hv(D_MAXF);
+                                    bool ok = pass && (mf == 0u || cntf <= mf);
                                     // further affine properties g(K) = c0 + sum_c w_c |K & mask_c| > 0
-                                    const uint32_t np = tab[D_NPROPS];
+                                    const uint32_t np = hv(D_NPROPS);
                                     if (np != 0u && __builtin_amdgcn_ballot_w64(ok) != 0) {
-                                        const uint32_t *pr = tab + tab[D_PROPS];
+                                        const uint32_t *pr = tab + hv(D_PROPS);
                                         for (uint32_t q = 0; q < np; ++q) {
                                             int64_t gv = (int32_t)pr[0];
                                             const uint32_t ncls = pr[1];
@@ -472,11 +495,12 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                                     }
                                     const uint64_t pball = __builtin_amdgcn_ballot_w64(pass);
                                     const uint64_t bal = __builtin_amdgcn_ballot_w64(ok);
-                                    n_ridge += (uint32_t)__builtin_popcountll(pball);
-                                    n_ubt += (uint32_t)__builtin_popcountll(pball & ~bal);
+                                    bk.n_ridge += (uint32_t)__builtin_popcountll(pball);
+                                    bk.n_ubt += (uint32_t)__builtin_popcountll(pball & ~bal);
                                     if (bal) {
                                         const uint32_t nbal = (uint32_t)__builtin_popcountll(bal);
-                                        item_cnt += nbal;
+                                        bk.item_cnt += nbal;
+                                        uint64_t out_pos = bk.out_pos, out_end = bk.out_end;
                                         if (out_pos + nbal > out_end) {
                                             // close the current chunk with sentinel
                                             // records and reserve a new one (one
@@ -498,10 +522,11 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                                             const uint64_t pos = out_pos + rk;
                                             if (pos < a.cap) {
                                                 a.surv[2 * pos] = x;
-                                                a.surv[2 * pos + 1] = inst;
+                                                a.surv[2 * pos + 1] = __builtin_amdgcn_readfirstlane(ci.instance);
                                             }
                                         }
-                                        out_pos += nbal;
+                                        bk.out_pos = out_pos + nbal;
+                                        bk.out_end = out_end;
                                     }
                                 }
                             }
@@ -523,8 +548,7 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                     if (t >= 12) {
                         // opaque copy: keeps the per-group tests from being
                         // hoisted out of the block loop as live lane masks
-                        int Gb = G, Wb = W, Qb = mqs;
-                        asm volatile("" : "+s"(Gb), "+s"(Wb), "+s"(Qb));
+                        const int Gb = (int)hv(D_G), Wb = (int)hv(D_W), Qb = (QS == 4) ? 4 : (int)hv(D_QS);
                         xor_row<GM, QS, WM>(P, row, ~0u, Gb, Wb, Qb);
                     }
                     s0 ^= row[0];
@@ -534,8 +558,9 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                 }
             }
         }
+        const uint32_t item_cnt = bk.item_cnt;
         if (item_cnt && lane == 0) atomicAdd(a.counts + inst, (unsigned long long)item_cnt);
-        wave_total += item_cnt;
+        bk.wave_total += item_cnt;
         __syncthreads();
         if (tid == 0 && a.times) {
             a.times[2 * it] = t_start;
@@ -543,6 +568,8 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
         }
     }
     // close this wave's output chunk and publish its totals
+    const uint64_t out_pos = bk.out_pos, out_end = bk.out_end, wave_total = bk.wave_total;
+    const uint32_t n_cand = bk.n_cand, n_ridge = bk.n_ridge, n_ubt = bk.n_ubt, n_pass = bk.n_pass;
     for (uint64_t e0 = out_pos + (uint64_t)lane; e0 < out_end && e0 < a.cap; e0 += 64) {
         a.surv[2 * e0] = 0;
         a.surv[2 * e0 + 1] = ~0ull;
