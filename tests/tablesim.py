@@ -120,41 +120,53 @@ def survivors_direct(tab):
 
 
 def survivors_walk(tab, cbits=7):
-    """Replays the GPU walk: lanes = chunks of 2^cbits Gray indices."""
+    """Replays the GPU walk: lanes = chunks of 2^cbits Gray indices.
+
+    The fast filter follows the 4 group-0 words step by step.  P, the full
+    state, is the lane's state at the start of the current 4096-step segment:
+    a passing step r of the chunk is rebuilt as P ^ S(gray(r) mod 2^12) from
+    four 8-row tables of the Gray bits 0-2, 3-5, 6-8 and 9-11, because
+    gray(i0 + r) = gray(i0) ^ gray(r) for a 2^c-aligned i0, and bit 12 of r
+    (the segment parity) toggles Gray bit 11.
+    """
     h = header(tab)
     R = rows(tab)
     kp, k = h["kp"], h["k"]
     c = min(max(cbits, 7), kp)
-    # U[v]: state contribution of the 6-bit low vector v (64 rows staged in LDS)
-    U = np.zeros((64, R.shape[1]), dtype=np.uint64)
-    for v in range(64):
-        U[v] = state(R[:6], v)
+    # T[b][v]: XOR of the rows 3b + j over the set bits j of v (rows >= kp are zero)
+    T = np.zeros((4, 8, R.shape[1]), dtype=np.uint64)
+    for b in range(4):
+        for v in range(8):
+            T[b][v] = state(R[3 * b:min(3 * b + 3, kp)], v & ((1 << max(0, min(3, kp - 3 * b))) - 1))
     out = []
     for j in range(1 << (kp - c)):
         i0 = j << c
         x0 = i0 ^ (i0 >> 1)
-        P = state(R, x0 & ~63)
-        assert (x0 & 63) == 0
+        P = state(R, x0)
         s4 = P[:4].copy()
-        for blk in range(1 << (c - 6)):
-            fire = []
+        nblk = 1 << (c - 6)
+        for blk in range(nblk):
+            cand = []
             for s in range(64):
                 if at_least3(slots4(s4, 0)) == 0:
-                    fire.append(s)
+                    cand.append(s)
                 if s < 63:
                     t = (s + 1 & -(s + 1)).bit_length() - 1
                     s4 ^= R[t, :4]
-            for s in fire:
-                low = (s ^ (s >> 1)) ^ ((blk & 1) << 5)
-                v = P ^ U[low]
-                i = i0 + (blk << 6) + s
+            seg = blk >> 6
+            for s in cand:
+                r12 = ((blk & 63) << 6) | s
+                g12 = (r12 ^ (r12 >> 1)) ^ ((seg & 1) << 11)
+                v = P ^ T[0][g12 & 7] ^ T[1][(g12 >> 3) & 7] ^ T[2][(g12 >> 6) & 7] ^ T[3][g12 >> 9]
+                i = i0 + (seg << 12) + r12
                 x = i ^ (i >> 1)
                 assert np.array_equal(v, state(R, x))
                 if x and (x >> k) == 0 and accept(h, v):
                     out.append(x)
-            if blk + 1 < (1 << (c - 6)):
+            if blk + 1 < nblk:
                 t = 6 + ((blk + 1) & -(blk + 1)).bit_length() - 1
-                P ^= R[t]
+                if t >= 12:
+                    P ^= R[t]
                 s4 ^= R[t, :4]
     return sorted(out)
 

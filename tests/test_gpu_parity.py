@@ -62,6 +62,18 @@ def test_single_n6_m10(E):
     assert sets[0] == want
 
 
+def test_single_chunks_across_segments(E):
+    # 2^14-step chunks: each lane's state P changes at the 4096-step segment
+    # boundaries inside its chunk, and candidates of odd segments use Gray
+    # bit 11 toggled by the segment parity
+    inst = W.single(E.kdim)
+    p = E.prepare(inst.n, inst.m, lam=inst.lam)
+    res, sets = run(E, [p], cbits=14, wg_size=64)
+    want = oracle_sets([p])[0]
+    assert sets[0] == want
+    assert int(res.counts[0]) == len(want) == res.total
+
+
 def test_graphs_many_parents(E):
     # n = 2: ridges are vertices; K_7 and K_8 have 6 and 7 parents per ridge
     preps = []

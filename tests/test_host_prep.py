@@ -89,6 +89,15 @@ def test_walk_with_larger_chunks():
     assert TS.survivors_walk(p.table, cbits=9) == TS.survivors_direct(p.table)
 
 
+def test_walk_across_4096_step_segments():
+    # chunks of 2^13 steps: P changes once inside each chunk (t = 12), and
+    # the second segment's candidates use Gray bit 11 toggled by its parity
+    inst = [i for i in W.batch(O.kdim_of, count=64) if 14 <= i.meta["k"] <= 15][0]
+    p = E.prepare(inst.n, inst.m, lam=inst.lam)
+    assert p.k >= 14
+    assert TS.survivors_walk(p.table, cbits=13) == TS.survivors_direct(p.table)
+
+
 def test_pack_rejects_large_k_and_bad_input():
     lib = L.lib()
     info = L.InstanceInfo()
