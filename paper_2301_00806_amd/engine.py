@@ -564,6 +564,89 @@ class Sweeper:
                 e1.record(stream)
                 self.seg_events.append((sg.cls, e0, e1))
 
+    def launch_fetch(self, mode: int, wg_size: int = 256, grid: int = 0, stream=None,
+                     parts: int = 4, seg_events: bool = False):
+        """Sweep and copy the survivor records to pinned host memory, with the
+        copies overlapping the sweep: the largest segment is launched in
+        `parts` consecutive item ranges, the record-slot counter is snapshot
+        on `stream` after every launch (the next launch only reserves slots
+        above it, and every wave closes its slot chunk before its launch
+        ends), and each finished slot range is copied on a second stream
+        while the next launch runs.  Returns a numpy view of all used record
+        slots.  With seg_events, self.seg_events holds one (class, start,
+        end) event pair per segment, bracketing all of its launches."""
+        torch = self.torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        segs = list(self._segments or [Segment(None, 0, 0)])
+        if mode == L.SCHED_PACKED:
+            parts = 1
+        big = max(range(len(segs)), key=lambda i: segs[i].end - segs[i].start)
+        runs = []  # (segment index, start, end)
+        for i, sg in enumerate(segs):
+            n = sg.end - sg.start
+            k = max(1, min(parts, n)) if i == big else 1
+            cuts = [sg.start + (n * j) // k for j in range(k + 1)]
+            runs += [(i, cuts[j], cuts[j + 1]) for j in range(k)]
+        if getattr(self, "_snap", None) is None or self._snap.numel() < len(runs):
+            self._snap = torch.zeros(max(8, len(runs)), dtype=torch.int64, device=self.surv.device)
+            self._snap_host = torch.zeros(max(8, len(runs)), dtype=torch.int64, pin_memory=True)
+        if getattr(self, "_copy_stream", None) is None:
+            self._copy_stream = torch.cuda.Stream(device=self.surv.device)
+        if getattr(self, "_pinned", None) is None or self._pinned.shape[0] < self.cap:
+            self._pinned = torch.empty((max(self.cap, 1), 2), dtype=torch.int64, pin_memory=True)
+        items = self._items_host
+        ends, starts, self.seg_events = [], {}, []
+        for r, (i, a0, a1) in enumerate(runs):
+            sg = segs[i]
+            if seg_events and i not in starts:
+                starts[i] = torch.cuda.Event(enable_timing=True)
+                starts[i].record(stream)
+            cb = self.batch.c_batch if sg.cls is None else self.batch.class_batches[sg.cls]
+            n = a1 - a0
+            s = L.Sched(mode=mode, wg_size=wg_size, grid=grid,
+                        flags=L.FLAG_ACCUMULATE if r else 0,
+                        d_items=self._items_dev.data_ptr() + 16 * a0,
+                        h_items=items.ctypes.data + 16 * a0 if n else None,
+                        num_items=n, d_scratch=self.scratch.data_ptr(),
+                        d_item_times=(self._times.data_ptr() + 16 * a0) if self._times is not None else None,
+                        d_bin_offsets=None)
+            if mode == L.SCHED_PACKED:  # never split: the bins cover the whole segment
+                bins = self._seg_bins[i] if self._segments else None
+                if bins is None:
+                    raise ValueError("packed mode needs per-segment bins")
+                s.d_bin_offsets, s.grid = bins.data_ptr(), len(bins) - 1
+            st = L.lib().wpm_enumerate(ctypes.byref(cb), ctypes.byref(s), self.surv.data_ptr(),
+                                       self.cap, self.counts.data_ptr(), self.total.data_ptr(),
+                                       self.stats.data_ptr(), ctypes.c_void_p(stream.cuda_stream))
+            L.check("wpm_enumerate", st)
+            with torch.cuda.stream(stream):
+                self._snap[r:r + 1].copy_(self.total[1:2])
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            ends.append(ev)
+            if seg_events and (r + 1 == len(runs) or runs[r + 1][0] != i):
+                e1 = torch.cuda.Event(enable_timing=True)
+                e1.record(stream)
+                self.seg_events.append((sg.cls, starts[i], e1))
+        # end of the sweep on `stream` (before the host waits for copies)
+        self.launch_end = torch.cuda.Event(enable_timing=True)
+        self.launch_end.record(stream)
+        cs = self._copy_stream
+        prev = 0
+        for r, ev in enumerate(ends):
+            cs.wait_event(ev)
+            with torch.cuda.stream(cs):
+                self._snap_host[r:r + 1].copy_(self._snap[r:r + 1], non_blocking=True)
+            cs.synchronize()
+            cur = min(int(self._snap_host[r]), self.cap)
+            if cur > prev:
+                with torch.cuda.stream(cs):
+                    self._pinned[prev:cur].copy_(self.surv[prev:cur], non_blocking=True)
+                prev = cur
+        cs.synchronize()
+        return self._pinned[:prev].numpy()
+
     def fetch_records(self, n: Optional[int] = None):
         """Copy the first n record slots (default: all used slots) into a
         pinned host buffer (allocated once) and return a numpy view of them.
