@@ -449,7 +449,8 @@ int wpm_persistent_grid(const wpm_batch *batch, int32_t wg_size, int32_t *grid);
  *   d_stats     optional [8] uint64 device counters: [0] candidates (vectors
  *               passing the fast filter), [1] vectors passing every ridge
  *               check, [2] vectors rejected by the upper bound, [3] wave
- *               passes over the queued candidates
+ *               passes over the listed candidates, [4] wave steps whose
+ *               candidates overflowed the list and were rechecked
  * Asynchronous: returns after enqueueing.  Items must describe chunks inside
  * each instance's 2^max(k,7) Gray range (checked on the host for PLAIN mode
  * and by wpm_build_queue's construction otherwise).

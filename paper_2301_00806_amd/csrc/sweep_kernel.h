@@ -189,12 +189,12 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
     // [out_pos, out_end) is the wave's current chunk of record slots.
     struct Book {
         uint64_t out_pos, out_end, wave_total;
-        uint32_t item_cnt, n_cand, n_ridge, n_ubt, n_pass, pad;
+        uint32_t item_cnt, n_cand, n_ridge, n_ubt, n_pass, n_redo;
     };
     __shared__ Book s_book[512 / 64];
     Book &bk = s_book[tid >> 6];
     bk.out_pos = bk.out_end = bk.wave_total = 0;
-    bk.item_cnt = bk.n_cand = bk.n_ridge = bk.n_ubt = bk.n_pass = 0;
+    bk.item_cnt = bk.n_cand = bk.n_ridge = bk.n_ubt = bk.n_pass = bk.n_redo = 0;
     // this wave's candidate list: entries (step r12 << 6) | lane
     uint32_t *lds_W = lds_dyn + (tid >> 6) * LIST_CAP;
 
@@ -383,6 +383,7 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                     const uint64_t sbase = (blk >> 6) << 12;
                     const uint32_t par = (uint32_t)((blk >> 6) & 1ull) << 11;
                     uint64_t rd = redo;
+                    bk.n_redo += (uint32_t)__builtin_popcountll(redo);
                     for (;;) {
                         // overflow steps: every lane rechecks the fast filter
                         // on the rebuilt group-0 words; passing lanes are listed
@@ -570,16 +571,18 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
     // close this wave's output chunk and publish its totals
     const uint64_t out_pos = bk.out_pos, out_end = bk.out_end, wave_total = bk.wave_total;
     const uint32_t n_cand = bk.n_cand, n_ridge = bk.n_ridge, n_ubt = bk.n_ubt, n_pass = bk.n_pass;
+    const uint32_t n_redo = bk.n_redo;
     for (uint64_t e0 = out_pos + (uint64_t)lane; e0 < out_end && e0 < a.cap; e0 += 64) {
         a.surv[2 * e0] = 0;
         a.surv[2 * e0 + 1] = ~0ull;
     }
     if (lane == 0 && wave_total) atomicAdd(a.total, (unsigned long long)wave_total);
-    if (a.stats && lane == 0 && (n_cand | n_ridge | n_ubt | n_pass)) {
+    if (a.stats && lane == 0 && (n_cand | n_ridge | n_ubt | n_pass | n_redo)) {
         atomicAdd(a.stats + 0, (unsigned long long)n_cand);
         atomicAdd(a.stats + 1, (unsigned long long)n_ridge);
         atomicAdd(a.stats + 2, (unsigned long long)n_ubt);
         atomicAdd(a.stats + 3, (unsigned long long)n_pass);
+        atomicAdd(a.stats + 4, (unsigned long long)n_redo);
     }
 }
 

@@ -82,6 +82,9 @@ def test_graphs_many_parents(E):
         preps.append(E.prepare(2, v, facets=F, max_facets=0))
     res, sets = run(E, preps)
     assert sets == oracle_sets(preps)
+    # dense candidates: blocks overflow the wave's candidate list, so the
+    # overflow steps are rechecked from the scalar mask (stats[4])
+    assert int(res.stats[4]) > 0
 
 
 def test_batch_mixed(E):
