@@ -113,6 +113,36 @@ def test_schedule_invariance(E):
     assert np.array_equal(res.counts, ref)
 
 
+def test_overlapped_record_copies_match_plain_launch(E):
+    # Sweeper.launch_fetch splits the largest class into launches and copies
+    # each finished slot range while the next launch runs: the same counts
+    # and the same multiset of records as one launch and one copy
+    from paper_2301_00806_amd import scheduler as S
+    insts = [i for i in W.batch(E.kdim, count=96) if i.meta["k"] <= 24][:48]
+    preps = E.prepare_many(insts)
+    batch = E.DeviceBatch(preps)
+    sw = E.Sweeper(batch, cap=1 << 22)
+
+    def real(rec):
+        r = np.asarray(rec)
+        r = r[r[:, 1] != -1]  # sentinel slots carry the instance ~0
+        return r[np.lexsort((r[:, 0], r[:, 1]))]
+
+    for policy in ("dynamic", "static", "packed"):
+        plan = S.make_plan(batch, policy, cbits=9, wg=256)
+        _say(f"[gpu] launch_fetch {policy}: {len(plan.items)} items, {len(plan.segments)} segments")
+        sw.set_items(plan.items, segments=plan.segments)
+        got = real(sw.launch_fetch(plan.mode, wg_size=256, parts=4).copy())
+        got_counts = sw.counts[:len(preps)].cpu().numpy().copy()
+        sw.set_items(plan.items, segments=plan.segments)
+        sw.launch(plan.mode, wg_size=256)
+        want = real(sw.fetch_records().copy())
+        want_counts = sw.counts[:len(preps)].cpu().numpy()
+        assert np.array_equal(got_counts, want_counts), policy
+        assert np.array_equal(got, want), policy
+        assert len(got) == int(want_counts.sum())
+
+
 def test_capacity_overflow_keeps_counts_exact(E):
     from paper_2301_00806_amd import _lib as L
     f = W.fano()
