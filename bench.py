@@ -38,6 +38,25 @@ INT32_PEAK = 256 * 128 * 2.4e9
 ALG_OPS_PER_VECTOR = 7             # fast filter: 4 XOR + 2 threshold ops + 1 compare
 
 
+def ops_alg_plain(p) -> int:
+    """Work per kernel vector of the plain per-ridge check (the paper's
+    kernel in bit-mask form): W XORs for the Gray step, for every ridge with
+    at least 4 parents an AND and a popcount per facet word holding one of
+    its parents plus one compare, and W popcounts plus a compare for the
+    facet bound."""
+    facets = [int(f) for f in p.facets]
+    words, parents = {}, {}
+    for j, f in enumerate(facets):
+        v = f
+        while v:
+            r = f & ~(v & -v)
+            words.setdefault(r, set()).add(j >> 5)
+            parents[r] = parents.get(r, 0) + 1
+            v &= v - 1
+    W = (len(facets) + 31) // 32
+    return W + sum(2 * len(words[r]) + 1 for r in words if parents[r] >= 4) + W + 1
+
+
 WORKLOADS = {
     "learned": "learned-scheduler batch: {count} lambda = [I_n | 4 uniform], n = 5..8, m = n + 4, k <= 36",
     "batch": "batch: {count} lambda = [I_n | 4 uniform], n = 4..7, m = n + 4, 12 <= k <= 32",
@@ -62,11 +81,11 @@ def build_workload(count: int, workload: str = "learned", seed_start: int = 0):
     return insts, preps
 
 
-def oracle_counts_match(counts, n_inst):
-    """Per-instance counts against the oracle's, stored for the 16384-instance
-    workload by tests/golden/make_learned_counts.py (None for other sizes)."""
-    path = os.path.join(ROOT, "tests", "golden", "learned16384_counts.json")
-    if n_inst != 16384 or not os.path.exists(path):
+def oracle_counts_match(counts, workload, n_inst):
+    """Per-instance counts against the oracle's, stored for each workload at
+    its full size by tests/golden/make_counts.py (None for other sizes)."""
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}{n_inst}_counts.json")
+    if not os.path.exists(path):
         return None
     with open(path) as f:
         gold = np.array(json.load(f)["counts"], dtype=np.uint64)
@@ -136,6 +155,7 @@ def main():
     ap.add_argument("--instances", type=int, default=0, help="0 = the workload's own size")
     ap.add_argument("--cbits", type=int, default=0, help="lane chunk bits (0 = autotuned)")
     ap.add_argument("--wg", type=int, default=0, help="workgroup size (0 = autotuned)")
+    ap.add_argument("--waves", type=int, default=0, help="kernel register budget: 7 or 8 waves per SIMD (0 = autotuned)")
     ap.add_argument("--max-items", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-static", action="store_true")
@@ -182,13 +202,14 @@ def main():
     log(f"sum 2^k = {vectors:.4e}; tables {batch.table_bytes / 1e6:.1f} MB in HBM")
     stream = torch.cuda.current_stream()
     tuned = None
-    if args.cbits == 0 or args.wg == 0:
+    if args.cbits == 0 or args.wg == 0 or args.waves == 0:
         from paper_2301_00806_amd import tune as T
         tuned = T.tune(preps, log=log)
         log(f"autotuner ({'cached' if tuned['cached'] else 'measured'}, {tuned['key']}): "
             f"cbits={tuned['cbits']} wg={tuned['wg']}")
         args.cbits = args.cbits or tuned["cbits"]
         args.wg = args.wg or tuned["wg"]
+        args.waves = args.waves or tuned.get("waves", 0)
     sw = E.Sweeper(batch, cap=args.cap)
 
     # ---- learned part: labels from timed sweeps of the batch workload, MLP
@@ -217,7 +238,7 @@ def main():
         plan = make()
         for _ in range(warmup):
             sw.set_items(plan.items, segments=plan.segments)
-            sw.launch_fetch(plan.mode, wg_size=args.wg, stream=stream, parts=args.parts)
+            sw.launch_fetch(plan.mode, wg_size=args.wg, stream=stream, parts=args.parts, waves=args.waves)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -231,10 +252,10 @@ def main():
             # the sweep, with the survivor records copied to pinned host
             # memory while the later sub-launches still run
             rec = sw.launch_fetch(plan.mode, wg_size=args.wg, stream=stream, parts=args.parts,
-                                  seg_events=True)
+                                  seg_events=True, waves=args.waves)
             e1 = sw.launch_end
             counts = sw.counts[:n_inst].cpu()          # synchronises the stream
-            tot, slots = (int(v) for v in sw.total.cpu())
+            tot, slots = (int(v) for v in sw.total.cpu()[:2])
             if slots > sw.cap:
                 raise SystemExit(f"survivor buffer too small: {slots} > {sw.cap}")
             assert len(rec) == slots
@@ -259,7 +280,7 @@ def main():
     # that record copies overlap it); its events time the dominant kernel
     plan = plan_learned()
     sw.set_items(plan.items, segments=plan.segments)
-    sw.launch(plan.mode, wg_size=args.wg, stream=stream, seg_events=True)
+    sw.launch(plan.mode, wg_size=args.wg, stream=stream, seg_events=True, waves=args.waves)
     torch.cuda.synchronize()
     seg_ms = {(None if cls is None else int(cls)): a0.elapsed_time(a1) for cls, a0, a1 in sw.seg_events}
     assert np.array_equal(sw.counts[:len(preps)].cpu().numpy().astype(np.uint64), res_b.counts)
@@ -276,7 +297,7 @@ def main():
         t1 = time.perf_counter()
         plan = plan_learned()
         sw.set_items(plan.items, segments=plan.segments)
-        sw.launch(plan.mode, wg_size=args.wg, stream=stream)
+        sw.launch(plan.mode, wg_size=args.wg, stream=stream, waves=args.waves)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         cnt_e, words_e, _ = sw.collect_raw()
@@ -288,14 +309,15 @@ def main():
                "note": "collect = records to host + expansion to sorted facet lists, 16 host threads"}
         log(f"end to end: {e2e}")
         del words_e
-    # the dominant launch: the template class holding most of the vectors
+    # the dominant launch: the launch class holding most of the vectors
     cls_vec = {}
     for p, c in zip(preps, batch.cls):
         if p.k > 0:
             cls_vec[int(c)] = cls_vec.get(int(c), 0) + (1 << p.k)
     dom = max(cls_vec, key=cls_vec.get)
     dom_ms = seg_ms[dom]
-    dom_name = "sweep_kernel<%d, %d, %d>" % (dom // 10000, (dom // 100) % 100, dom % 100)
+    waves_used = args.waves if args.waves in (7, 8) else 8
+    dom_name = "sweep_kernel<%d> (rows of at most %d words)" % (waves_used, dom)
     log(f"dominant launch {dom_name}: {cls_vec[dom]:.4e} vectors in {dom_ms:.2f} ms "
         f"({cls_vec[dom] / dom_ms * 1e3:.3e} vectors/s); per-class ms {seg_ms}")
     out = {}
@@ -368,6 +390,12 @@ def main():
         torch.cuda.synchronize()
 
     achieved = ALG_OPS_PER_VECTOR * cls_vec[dom] / (dom_ms * 1e-3) / 1e12
+    # the same launch priced at the plain per-ridge check's work per vector
+    # (AND + popcount per parent word of every critical ridge), weighted by 2^k
+    plain_ops = sum(float(1 << p.k) * ops_alg_plain(p) for p, c in zip(preps, batch.cls)
+                    if int(c) == dom and p.k > 0)
+    plain_per_vec = plain_ops / cls_vec[dom]
+    effective = plain_ops / (dom_ms * 1e-3) / 1e12
     probe = E.valu_probe(0, 4)
     counters = None
     cpath = os.path.join(ROOT, "profiles", "sweep_counters.json")
@@ -405,12 +433,11 @@ def main():
         "data": "synthetic (seeded SplitMix64 inputs)",
         "config": {"workload": WORKLOADS[args.workload].format(count=len(preps)),
                    "instances": len(preps), "sum_2k": vectors, "cbits": args.cbits,
-                   "wg_size": args.wg, "record_copy_parts": args.parts,
+                   "wg_size": args.wg, "waves_per_simd": waves_used, "record_copy_parts": args.parts,
                    "schedule": f"learned: {args.learned_policy}, LPT on MLP-predicted cost"},
         "wpm_total": int(res_b.total),
         "wpm_counts_sha256": __import__("hashlib").sha256(res_b.counts.tobytes()).hexdigest(),
-        "wpm_counts_match_oracle": oracle_counts_match(res_b.counts, len(preps))
-        if args.workload == "learned" else None,
+        "wpm_counts_match_oracle": oracle_counts_match(res_b.counts, args.workload, len(preps)),
         "kernel_ms": k_b,
         "kernel_ms_median": kern_med,
         "end_to_end": e2e,
@@ -418,11 +445,17 @@ def main():
         "pruned": pruned,
         "cost_model": model_err,
         "autotune": None if tuned is None else {"key": tuned["key"], "cbits": tuned["cbits"],
-                                                "wg": tuned["wg"], "cached": tuned["cached"]},
+                                                "wg": tuned["wg"], "waves": tuned.get("waves"),
+                                                "cached": tuned["cached"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": INT32_PEAK / 1e12,
                      "unit": "Tops/s (int32 VALU lane-ops)", "frac": achieved / (INT32_PEAK / 1e12),
                      "traffic": traffic, "kernel": dom_name, "kernel_ms": dom_ms,
                      "vectors_per_launch": cls_vec[dom], "ops_per_vector": ALG_OPS_PER_VECTOR,
+                     "ops_alg_plain_per_vector": plain_per_vec,
+                     "effective_plain": effective, "effective_plain_frac": effective / (INT32_PEAK / 1e12),
+                     "note": "frac prices a vector at the fast filter's 7 int32 ops; effective_plain prices it "
+                             "at the plain per-ridge AND+popcount check of the same launch (saved work, "
+                             "not skipped work: every count equals the oracle's)",
                      "measured_int32_xor_peak": probe / 1e12,
                      "executed_frac": None if counters is None else
                      counters["executed_lane_ops_per_s"] / INT32_PEAK,

@@ -63,6 +63,9 @@ enum {
 #define WPM_MAX_SLOTS 8     /* parents-1 of a critical ridge */
 #define WPM_LOW_BITS 6      /* Gray steps unrolled per block: 2^6 */
 #define WPM_TABLE_ROWS 32   /* Gray-bit lookup rows staged per instance: 4 tables of 2^3 */
+#define WPM_MAX_ROW_WORDS 160 /* words per row of a packed table (4 + 15 groups x 8 + 32) */
+#define WPM_TOTAL_WORDS 4   /* uint64 words of the d_total argument of wpm_enumerate */
+#define WPM_LANE_WINDOW 512 /* an item's lane chunks lie in one aligned window of this many */
 
 /* Human-readable text of a status code (static storage). */
 const char *wpm_strerror(int status);
@@ -209,12 +212,10 @@ int wpm_facet_conditions(int n, int m, const uint32_t *facets, int32_t M, const 
  * critical ridges (the most rejecting ones, in the packer's greedy order),
  * each with at most WPM_MAX_SLOTS + 1 parents.  Any further critical ridges
  * (and ridges with more parents) are deferred: the table lists their parents,
- * and wpm_enumerate follows the sweep with a verification pass that checks
- * them on every survivor record, retires the records that fail (instance
- * ~0) and takes them off the counts.  Results and counts stay exact, except
- * after a record-buffer overflow: records that were not stored cannot be
- * verified, so the counts of instances with deferred ridges are then upper
- * bounds.
+ * and the sweep checks them (degree <= 2 in K, Proposition 2.1) on every
+ * vector that passes the resident groups, before it counts or records it.
+ * Results and counts are exact in every case, also after a record-buffer
+ * overflow.
  */
 typedef struct wpm_conditions {
     const uint32_t *offset;
@@ -398,21 +399,22 @@ int wpm_build_pruned_queue(const wpm_blocks *blocks, const float *cost, const in
 int wpm_pack_bins(const wpm_item *items, int64_t n, const float *cost, int32_t bins,
                   wpm_item *out_items, int64_t *out_offsets, double *max_load);
 
-/* Device-resident batch. */
+/* Device-resident batch.  One kernel serves every instance shape: it reads
+ * the ridge groups, slot stride and facet words from each table's header.
+ * max_row_words and max_kp size the workgroup's LDS; an item whose table is
+ * larger is skipped and counted as malformed (d_total[2]). */
 typedef struct wpm_batch {
     int32_t num_instances;
-    int32_t max_row_words;     /* max info.row_words over the batch (LDS sizing) */
-    int32_t max_groups;        /* max info.groups */
-    int32_t max_slots;         /* max info.slots (4 or 8) */
-    int32_t max_words;         /* max info.W */
-    int32_t max_kp;            /* max over the batch of max(k, 7) (LDS sizing) */
+    int32_t max_row_words;     /* max info.row_words over the tables swept (multiple of 4, <= WPM_MAX_ROW_WORDS) */
+    int32_t max_groups;        /* max info.groups (informational) */
+    int32_t max_slots;         /* max info.slots (informational) */
+    int32_t max_words;         /* max info.W (informational) */
+    int32_t max_kp;            /* max over the tables swept of max(k, 7), <= WPM_MAX_K */
     const uint32_t *d_tables;  /* device: packed tables, concatenated (16-byte aligned each) */
     const int64_t *d_offsets;  /* device: word offset of each table in d_tables */
-    int32_t flags;             /* WPM_BATCH_DEFERRED: some table has deferred ridges */
+    int32_t flags;             /* reserved, 0 */
     int32_t reserved;
 } wpm_batch;
-
-#define WPM_BATCH_DEFERRED 1 /* run the verification pass of deferred ridges */
 
 #define WPM_FLAG_ACCUMULATE 1 /* do not clear d_counts, d_total, d_stats: add to them */
 
@@ -427,6 +429,8 @@ typedef struct wpm_sched {
     uint32_t *d_scratch;       /* device: >= 4 words (queue head), cleared by the call */
     uint64_t *d_item_times;    /* optional device [num_items][2]: start, end (s_memrealtime) */
     const int64_t *d_bin_offsets; /* PACKED mode: device [grid + 1] from wpm_pack_bins */
+    int32_t waves_per_simd;    /* register budget of the kernel: 7 or 8 waves per SIMD (0 = 8) */
+    int32_t reserved;
 } wpm_sched;
 
 /* Workgroups a persistent launch of this batch uses by default: the
@@ -434,26 +438,45 @@ typedef struct wpm_sched {
 int wpm_persistent_grid(const wpm_batch *batch, int32_t wg_size, int32_t *grid);
 
 /*
- * Sweep every item on `stream`.
+ * The weak pseudo-manifolds of every item's instance (Section 2.1, problem
+ * statement: every K with facets in F satisfying the properties G).  By
+ * Proposition 2.1 a complex K is a weak pseudo-manifold iff every entry of
+ * A K lies in {0, 2}; such K lie in ker_F2 A, so the sweep visits the kernel
+ * vectors x in Gray order (the enumeration of Section 2.1, with the paper's
+ * per-candidate ridge check of Section 2.3 in bit-sliced form) and keeps x
+ * when every critical ridge has degree <= 2, |K| <= max_facets (the
+ * upper-bound property of Section 4.2), every further property g(K) > 0, and
+ * x != 0 (x = 0 is kept only for an affine coset, where it is K*).  Each kept
+ * x is an output of Section 2.3's list, written as a record.
+ *   batch       device tables (wpm_pack_instance), see wpm_batch
+ *   sched       items (device, and a host copy in PLAIN mode), mode,
+ *               workgroup size, grid, register budget
  *   d_survivors [cap][2] uint64 device records {x, instance}.  Waves reserve
  *               record slots in chunks, so the slots used may exceed the
  *               results; unused slots hold the sentinel {0, ~0}.  Records are
  *               in no particular order; slots at or beyond cap are not written.
  *   d_counts    [num_instances] uint64 device; set to each instance's exact
  *               number of results (cleared by the call unless
- *               WPM_FLAG_ACCUMULATE: then a batch can be swept by several calls,
- *               for example one per kernel template class, into one set of counts)
- *   d_total     [2] uint64 device: [0] total results, [1] record slots used
- *               ([1] > cap: the caller needs a larger buffer and wpm_collect
- *               returns WPM_ECAP; counts stay exact)
+ *               WPM_FLAG_ACCUMULATE: then a batch can be swept by several calls
+ *               into one set of counts)
+ *   d_total     [WPM_TOTAL_WORDS] uint64 device: [0] total results, [1] record
+ *               slots used ([1] > cap: the caller needs a larger buffer and
+ *               wpm_collect returns WPM_ECAP; counts stay exact), [2] malformed
+ *               items skipped (wpm_collect then returns WPM_EINVAL), [3] 0
  *   d_stats     optional [8] uint64 device counters: [0] candidates (vectors
- *               passing the fast filter), [1] vectors passing every ridge
- *               check, [2] vectors rejected by the upper bound, [3] wave
- *               passes over the listed candidates, [4] wave steps whose
- *               candidates overflowed the list and were rechecked
- * Asynchronous: returns after enqueueing.  Items must describe chunks inside
- * each instance's 2^max(k,7) Gray range (checked on the host for PLAIN mode
- * and by wpm_build_queue's construction otherwise).
+ *               passing the fast filter), [1] vectors passing every resident
+ *               ridge group, [2] of those, vectors rejected by the facet bound,
+ *               the properties or a deferred ridge, [3] wave passes over the
+ *               listed candidates, [4] wave steps whose candidates overflowed
+ *               the list and were rechecked
+ * Items must lie inside their instance's 2^max(k,7) Gray range with
+ * 7 <= cbits <= max(k, 7), 1 <= lanes <= wg_size, and first mod
+ * WPM_LANE_WINDOW + lanes <= WPM_LANE_WINDOW (wpm_build_queue and
+ * wpm_build_pruned_queue emit such items); the kernel skips any other item
+ * and counts it in d_total[2].  PLAIN mode rejects items naming an unknown
+ * instance with WPM_EINVAL before launching.
+ * Asynchronous: returns after enqueueing on `stream`.  No device memory is
+ * allocated.
  */
 int wpm_enumerate(const wpm_batch *batch, const wpm_sched *sched, uint64_t *d_survivors,
                   uint64_t cap, uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats,
@@ -479,16 +502,22 @@ typedef struct wpm_host_instance {
 } wpm_host_instance;
 
 /*
- * Synchronise `stream`, copy counts and survivors to the host and expand each
- * survivor x into its facet list K = sum_t x_t K_t.
+ * The result set of Section 2.1's problem statement, per instance: every
+ * kept x becomes its complex K = sum_t x_t K_t (+ K* for a coset), listed by
+ * its facets.  Synchronises `stream`, copies counts and records to the host
+ * and expands them.
+ *   insts        [num] host views of the instances (facets, basis, offset)
+ *   d_survivors, cap, d_counts, d_total   as passed to wpm_enumerate
  *   h_counts     [num] receives the exact per-instance counts
  *   h_out        [out_cap] uint32; per instance, in canonical order, each
  *                result as [len, facet masks ascending]; results of one
  *                instance are sorted lexicographically
  *   h_offsets    [num + 1] int64: word offset of each instance's results
- *   out_words    receives the words needed
- * Returns WPM_ECAP if the survivor buffer overflowed (*total > cap) or
- * out_cap is too small.
+ *   out_words    receives the words needed (when the record buffer
+ *                overflowed: minus the record slots needed)
+ * Returns WPM_ECAP if the record buffer overflowed (d_total[1] > cap) or
+ * out_cap is too small, WPM_EINVAL if the sweep skipped malformed items or
+ * the records disagree with the counts.
  */
 int wpm_collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_survivors,
                 uint64_t cap, const uint64_t *d_counts, const uint64_t *d_total,

@@ -11,7 +11,9 @@ WPM_OK, WPM_EINVAL, WPM_ECAP, WPM_EKMAX, WPM_EHIP, WPM_ELIMIT = 0, -1, -2, -3, -
 SCHED_PLAIN, SCHED_STATIC, SCHED_DYNAMIC, SCHED_PACKED = 0, 1, 2, 3
 FLAG_ACCUMULATE = 1
 CX_FULL_PICARD, CX_SEED = 1, 2
-BATCH_DEFERRED = 1
+TOTAL_WORDS = 4
+MAX_ROW_WORDS = 160
+LANE_WINDOW = 512
 MAX_K = 64
 
 c_u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -62,7 +64,8 @@ class Sched(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("d_items", ctypes.c_void_p),
                 ("h_items", ctypes.c_void_p), ("num_items", ctypes.c_int64),
                 ("d_scratch", ctypes.c_void_p), ("d_item_times", ctypes.c_void_p),
-                ("d_bin_offsets", ctypes.c_void_p)]
+                ("d_bin_offsets", ctypes.c_void_p), ("waves_per_simd", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class HostInstance(ctypes.Structure):

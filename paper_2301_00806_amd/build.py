@@ -1,7 +1,11 @@
 """Build libwpm.so (host prep + HIP kernels for gfx950) in place.
 
-Every source is compiled with hipcc; the four kernel instantiation units build
-in parallel.  Packed FP32 instructions are disabled for all device code.
+Every source is compiled with hipcc, in parallel.  Packed FP32 instructions
+are disabled for all device code.  The sweep unit is compiled without the
+machine-level loop-invariant code motion pass: it would hoist values used
+only by the rare check paths (lane addresses, constants) out of the sweep
+loop and keep them in registers through it, which makes the register
+allocator spill them to scratch memory.
 """
 from __future__ import annotations
 
@@ -21,7 +25,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 SOURCES = ["prep.cpp", "prune.cpp", "conditions.cpp", "orbits.cpp", "complexes.cpp", "sched.cpp", "capi.cpp", "engine.hip", "mlp.hip", "probe.hip",
-           "sweep_g2.hip", "sweep_g4.hip", "sweep_g8.hip", "sweep_g16.hip"]
+           "sweep.hip"]
+EXTRA = {"sweep.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
 def _compile(src: str) -> str:
@@ -30,6 +35,7 @@ def _compile(src: str) -> str:
     cmd = [HIPCC] + COMMON
     if src.endswith(".hip"):
         cmd += DEVICE
+    cmd += EXTRA.get(src, [])
     cmd += ["-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)

@@ -21,56 +21,6 @@ __global__ void zero_u64(unsigned long long *p, int64_t n) {
     if (i < n) p[i] = 0ull;
 }
 
-// Verification pass for deferred ridges: every survivor record of an
-// instance whose table lists deferred ridges has its facet vector K rebuilt
-// from the table rows; if some deferred ridge has more than 2 parents in K,
-// the record is retired (instance ~0) and taken off the counts.
-__global__ void verify_deferred(const uint32_t *__restrict__ tables,
-                                const int64_t *__restrict__ offsets, int32_t num_instances,
-                                uint64_t *surv, uint64_t cap, const unsigned long long *slots,
-                                unsigned long long *counts, unsigned long long *total) {
-    const uint64_t n = *slots < cap ? *slots : cap;
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
-         r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t inst = surv[2 * r + 1];
-        if (inst >= (uint64_t)num_instances) continue;  // unused slot or retired record
-        const uint32_t *tab = tables + offsets[inst];
-        const uint32_t nd = tab[HDR_NDEFER];
-        if (nd == 0u) continue;
-        const uint64_t x = surv[2 * r];
-        const int kp = (int)tab[HDR_KP], W = (int)tab[HDR_W], G = (int)tab[HDR_G];
-        const int QS = (int)tab[HDR_QS], RS = (int)tab[HDR_RS];
-        const int koff = 4 + (G - 1) * QS;
-        const uint32_t *rows = tab + WPM_HDR_WORDS;
-        uint32_t K[32];
-        for (int w = 0; w < 32; ++w)
-            K[w] = (w < W && (tab[HDR_FLAGS] & HDR_FLAG_OFFSET)) ? rows[(size_t)kp * RS + koff + w] : 0u;
-        for (uint64_t b = x; b; b &= b - 1) {
-            const int t = __builtin_ctzll(b);
-            if (t >= kp) break;
-            for (int w = 0; w < W; ++w) K[w] ^= rows[(size_t)t * RS + koff + w];
-        }
-        const uint32_t *d = tab + tab[HDR_DEFER];
-        bool ok = true;
-        for (uint32_t q = 0; q < nd && ok; ++q) {
-            const uint32_t p = d[0];
-            uint32_t cnt = 0;
-            for (uint32_t j = 0; j < p; ++j) {
-                const uint32_t f = d[1 + j];
-                cnt += (K[(f >> 5) & 31u] >> (f & 31u)) & 1u;
-            }
-            ok = cnt <= 2u;
-            d += 1 + p;
-        }
-        if (!ok) {
-            atomicAdd(counts + inst, ~0ull);  // minus one
-            atomicAdd(total, ~0ull);
-            surv[2 * r] = 0;
-            surv[2 * r + 1] = ~0ull;
-        }
-    }
-}
-
 int hip_fail(const char *what, hipError_t e) {
     set_hip_error(what, (int)e, hipGetErrorString(e));
     return WPM_EHIP;
@@ -91,28 +41,8 @@ int zero(void *p, int64_t n, hipStream_t st) {
     return WPM_OK;
 }
 
-int pick_gm(int g) { return g <= 2 ? 2 : g <= 4 ? 4 : g <= 8 ? 8 : 16; }
-int pick_wm(int w) { return w <= 4 ? 4 : w <= 10 ? 10 : w <= 16 ? 16 : 32; }
-
-hipError_t launch(int gm, int qs, int wm, dim3 grid, dim3 block, size_t lds, hipStream_t st,
-                  const uint32_t *tables, const int64_t *offsets, const wpm_item *items,
-                  const KArgs &a) {
-    switch (gm) {
-        case 2: return launch_sweep_g2(qs, wm, grid, block, lds, st, tables, offsets, items, a);
-        case 4: return launch_sweep_g4(qs, wm, grid, block, lds, st, tables, offsets, items, a);
-        case 8: return launch_sweep_g8(qs, wm, grid, block, lds, st, tables, offsets, items, a);
-        default: return launch_sweep_g16(qs, wm, grid, block, lds, st, tables, offsets, items, a);
-    }
-}
-
-hipError_t occupancy(int gm, int qs, int wm, int *nb, int block, size_t lds) {
-    switch (gm) {
-        case 2: return occupancy_sweep_g2(qs, wm, nb, block, lds);
-        case 4: return occupancy_sweep_g4(qs, wm, nb, block, lds);
-        case 8: return occupancy_sweep_g8(qs, wm, nb, block, lds);
-        default: return occupancy_sweep_g16(qs, wm, nb, block, lds);
-    }
-}
+// Waves per SIMD of the kernel a schedule asks for (0: the default, 8).
+int pick_waves(int w) { return w == 7 ? 7 : 8; }
 }  // namespace
 
 void set_hip_error(const char *what, int code, const char *text) {
@@ -140,31 +70,23 @@ int device_query(int32_t *num_cus, int64_t *wallclock_khz, int32_t *lds_per_bloc
     return WPM_OK;
 }
 
+int persistent_grid_waves(const wpm_batch *b, int wg_size, int waves, int32_t *grid);
+
 int persistent_grid(const wpm_batch *b, int wg_size, int32_t *grid) {
+    return persistent_grid_waves(b, wg_size, 0, grid);
+}
+
+int persistent_grid_waves(const wpm_batch *b, int wg_size, int waves, int32_t *grid) {
     if (!b || !grid || wg_size < 64 || wg_size > 512 || (wg_size % 64)) return WPM_EINVAL;
-    if (b->max_groups < 1 || b->max_groups > WPM_MAX_GROUPS) return WPM_EINVAL;
-    if (b->max_slots != 4 && b->max_slots != 8) return WPM_EINVAL;
-    const int gm = pick_gm(b->max_groups), qs = b->max_slots, wm = pick_wm(b->max_words);
+    if (b->max_row_words < 4 || b->max_row_words > WPM_MAX_ROW_WORDS || (b->max_row_words & 3)) return WPM_EINVAL;
+    if (b->max_kp < 7 || b->max_kp > WPM_MAX_K) return WPM_EINVAL;
     const size_t lds = sweep_lds_bytes(b->max_kp, b->max_row_words, wg_size);
     int32_t cus = 0;
     int rc = device_query(&cus, nullptr, nullptr);
     if (rc) return rc;
     int nb = 0;
-    HIP_TRY(occupancy(gm, qs, wm, &nb, wg_size, lds));
+    HIP_TRY(occupancy_sweep(pick_waves(waves), &nb, wg_size, lds));
     *grid = std::max(1, nb) * cus;
-    return WPM_OK;
-}
-
-// The verification pass of deferred ridges, when the batch has any.
-int verify(const wpm_batch *b, uint64_t *d_surv, uint64_t cap, uint64_t *d_counts,
-           uint64_t *d_total, hipStream_t st) {
-    if (!(b->flags & WPM_BATCH_DEFERRED) || cap == 0) return WPM_OK;
-    const uint64_t nb = std::min<uint64_t>((cap + 255) / 256, 16384);
-    hipLaunchKernelGGL(verify_deferred, dim3((unsigned)nb), dim3(256), 0, st, b->d_tables,
-                       b->d_offsets, b->num_instances, d_surv, cap,
-                       (const unsigned long long *)(d_total + 1), (unsigned long long *)d_counts,
-                       (unsigned long long *)d_total);
-    HIP_TRY(hipGetLastError());
     return WPM_OK;
 }
 
@@ -172,9 +94,8 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
               uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats, void *stream) {
     if (!b || !s || !d_counts || !d_total || (cap > 0 && !d_surv)) return WPM_EINVAL;
     if (b->num_instances < 0 || !b->d_tables || !b->d_offsets) return WPM_EINVAL;
-    if (b->max_groups < 1 || b->max_groups > WPM_MAX_GROUPS) return WPM_EINVAL;
-    if (b->max_slots != 4 && b->max_slots != 8) return WPM_EINVAL;
-    if (b->max_words < 0 || b->max_words > 32 || b->max_row_words < 4) return WPM_EINVAL;
+    if (b->max_row_words < 4 || b->max_row_words > WPM_MAX_ROW_WORDS || (b->max_row_words & 3))
+        return WPM_EINVAL;
     if (b->max_kp < 7 || b->max_kp > WPM_MAX_K) return WPM_EINVAL;
     if (s->wg_size < 64 || s->wg_size > 512 || (s->wg_size % 64)) return WPM_EINVAL;
     if (s->num_items < 0 || (s->num_items > 0 && !s->d_items)) return WPM_EINVAL;
@@ -182,8 +103,9 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     if (s->mode == WPM_SCHED_PACKED && (!s->d_bin_offsets || s->grid < 1)) return WPM_EINVAL;
     if (s->mode == WPM_SCHED_PLAIN && s->num_items > 0 && !s->h_items) return WPM_EINVAL;
     if (s->mode == WPM_SCHED_DYNAMIC && !s->d_scratch) return WPM_EINVAL;
+    if (s->waves_per_simd != 0 && s->waves_per_simd != 7 && s->waves_per_simd != 8) return WPM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    const int gm = pick_gm(b->max_groups), qs = b->max_slots, wm = pick_wm(b->max_words);
+    const int waves = pick_waves(s->waves_per_simd);
     const size_t lds = sweep_lds_bytes(b->max_kp, b->max_row_words, s->wg_size);
     int32_t lds_max = 0;
     if (cap >= (UINT64_MAX >> 2)) return WPM_EINVAL;
@@ -194,7 +116,7 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     int st_rc;
     if (!(s->flags & WPM_FLAG_ACCUMULATE)) {
         if ((st_rc = zero(d_counts, b->num_instances, st))) return st_rc;
-        if ((st_rc = zero(d_total, 2, st))) return st_rc;
+        if ((st_rc = zero(d_total, WPM_TOTAL_WORDS, st))) return st_rc;
         if ((st_rc = zero(d_stats, 8, st))) return st_rc;
     }
     if (s->d_scratch && (st_rc = zero(s->d_scratch, 2, st))) return st_rc;
@@ -208,37 +130,42 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     a.cap = cap;
     a.counts = (unsigned long long *)d_counts;
     a.total = (unsigned long long *)d_total;
-    a.slots = (unsigned long long *)d_total + 1;
     a.stats = (unsigned long long *)d_stats;
     a.times = s->d_item_times;
     a.bins = s->d_bin_offsets;
+    a.num_instances = b->num_instances;
+    a.max_rs = b->max_row_words;
+    a.max_kp = b->max_kp;
     // persistent workgroups reserve output slots in chunks (few global
     // atomics); one-shot workgroups of the plain mode reserve exactly
     a.chunk = (s->mode == WPM_SCHED_PLAIN) ? 0 : 128;
     const dim3 block((unsigned)s->wg_size);
     if (s->mode == WPM_SCHED_PLAIN) {
-        // One launch per instance: a grid of exactly that instance's items.
+        // One launch per instance: a grid of exactly that instance's items
+        // (items naming an unknown instance are rejected before any launch;
+        // the kernel skips and counts any other malformed item).
+        for (int64_t i = 0; i < s->num_items; ++i)
+            if ((int64_t)s->h_items[i].instance >= (int64_t)b->num_instances) return WPM_EINVAL;
         a.mode = 0;
         int64_t i = 0;
         while (i < s->num_items) {
             int64_t e = i;
             while (e < s->num_items && s->h_items[e].instance == s->h_items[i].instance) ++e;
-            if ((int)s->h_items[i].instance >= b->num_instances) return WPM_EINVAL;
             a.item_base = i;
             a.num_items = e;
             const int64_t nb = e - i;
-            HIP_TRY(launch(gm, qs, wm, dim3((unsigned)nb), block, lds, st, b->d_tables, b->d_offsets,
-                           s->d_items, a));
+            HIP_TRY(launch_sweep(waves, dim3((unsigned)nb), block, lds, st, b->d_tables, b->d_offsets,
+                                 s->d_items, a));
             i = e;
         }
-        return verify(b, d_surv, cap, d_counts, d_total, st);
+        return WPM_OK;
     }
     int32_t grid = s->grid;
-    if (grid <= 0 && (rc = persistent_grid(b, s->wg_size, &grid))) return rc;
+    if (grid <= 0 && (rc = persistent_grid_waves(b, s->wg_size, waves, &grid))) return rc;
     a.mode = (s->mode == WPM_SCHED_STATIC) ? 1 : (s->mode == WPM_SCHED_DYNAMIC) ? 2 : 3;
-    HIP_TRY(launch(gm, qs, wm, dim3((unsigned)grid), block, lds, st, b->d_tables, b->d_offsets,
-                   s->d_items, a));
-    return verify(b, d_surv, cap, d_counts, d_total, st);
+    HIP_TRY(launch_sweep(waves, dim3((unsigned)grid), block, lds, st, b->d_tables, b->d_offsets,
+                         s->d_items, a));
+    return WPM_OK;
 }
 
 namespace {
@@ -285,11 +212,12 @@ int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv,
             (insts[i].k > 0 && !insts[i].basis) || (insts[i].M > 0 && !insts[i].facets))
             return WPM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    uint64_t tot[2] = {0, 0};
+    uint64_t tot[WPM_TOTAL_WORDS] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(h_counts, d_counts, sizeof(uint64_t) * (size_t)num, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(tot, d_total, sizeof(tot), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const uint64_t total = tot[0], slots = tot[1];
+    if (tot[2] != 0) return WPM_EINVAL;  // the sweep skipped malformed items
     if (slots > cap) {
         *out_words = -(int64_t)slots;  // record slots needed
         return WPM_ECAP;

@@ -298,18 +298,18 @@ def device_query():
 ITEM_DTYPE = np.dtype([("instance", "<u4"), ("cbits", "<u2"), ("lanes", "<u2"), ("first", "<u8")])
 
 
-def _gm(groups: int) -> int:
-    return 2 if groups <= 2 else 4 if groups <= 4 else 8 if groups <= 8 else 16
+# Row widths that bound a launch's LDS layout.  One kernel sweeps every
+# instance; a launch sizes each workgroup's LDS for its widest table, so
+# instances are launched in classes of similar width: 8 workgroups of 256
+# threads fit a compute unit up to 44 words per row (with kp <= 36), 6 up to
+# 64.
+LDS_CLASSES = (44, 64, 96, L.MAX_ROW_WORDS)
 
 
-def _wm(words: int) -> int:
-    return 4 if words <= 4 else 10 if words <= 10 else 16 if words <= 16 else 32
-
-
-def template_class(info) -> int:
-    """Code of the kernel instantiation an instance needs: (groups, slot
-    stride, facet words) rounded up to the instantiated sizes."""
-    return _gm(info.groups) * 10000 + info.slots * 100 + _wm(info.W)
+def lds_class(info) -> int:
+    """The launch class of an instance: the smallest row-width bound of
+    LDS_CLASSES that holds its table rows."""
+    return next(c for c in LDS_CLASSES if info.row_words <= c)
 
 
 class DeviceBatch:
@@ -344,7 +344,7 @@ class DeviceBatch:
                 else:
                     self.blocks[i].k = p.k
                     self.blocks[i].free_dims = p.k
-        self.cls = np.array([template_class(p.info) for p in self.preps], dtype=np.int64)
+        self.cls = np.array([lds_class(p.info) for p in self.preps], dtype=np.int64)
         self.c_batch = self._batch_of(self.preps)
         self.class_batches = {int(c): self._batch_of([p for p, q in zip(self.preps, self.cls) if q == c])
                               for c in np.unique(self.cls)}
@@ -358,8 +358,7 @@ class DeviceBatch:
             max_slots=max([p.info.slots for p in members] + [4]),
             max_words=max([p.info.W for p in members] + [1]),
             max_kp=max([max(p.k, 7) for p in members] + [7]),
-            d_tables=self.tables.data_ptr(), d_offsets=self.offsets.data_ptr(),
-            flags=L.BATCH_DEFERRED if any(p.info.n_deferred for p in members) else 0)
+            d_tables=self.tables.data_ptr(), d_offsets=self.offsets.data_ptr(), flags=0)
 
     @property
     def vectors(self) -> int:
@@ -423,8 +422,8 @@ def pack_bins(items: np.ndarray, bins: int, cost: Optional[np.ndarray] = None):
 
 
 def persistent_grid(batch: "DeviceBatch", wg_size: int, cls: Optional[int] = None) -> int:
-    """Workgroups of a persistent launch (of one template class, or of the
-    whole batch under its largest template)."""
+    """Workgroups of a persistent launch (of one launch class, or of the
+    whole batch with the LDS layout of its widest table)."""
     cb = batch.c_batch if cls is None else batch.class_batches[int(cls)]
     g = ctypes.c_int32(0)
     L.check("wpm_persistent_grid", L.lib().wpm_persistent_grid(ctypes.byref(cb), wg_size,
@@ -434,7 +433,7 @@ def persistent_grid(batch: "DeviceBatch", wg_size: int, cls: Optional[int] = Non
 
 @dataclass
 class Segment:
-    """Items [start, end) launched together under one kernel template."""
+    """Items [start, end) launched together (one launch class)."""
     cls: Optional[int]
     start: int
     end: int
@@ -442,7 +441,7 @@ class Segment:
 
 
 def split_by_class(batch: "DeviceBatch", items: np.ndarray):
-    """Stable grouping of items by their instance's template class, largest
+    """Stable grouping of items by their instance's launch class, widest
     class first -> (items, segments)."""
     if len(items) == 0:
         return items, []
@@ -458,7 +457,7 @@ def split_by_class(batch: "DeviceBatch", items: np.ndarray):
 
 def class_items(batch: "DeviceBatch", cbits: int, lanes: int, cost: Optional[np.ndarray] = None,
                 order: int = 0, min_items_per_instance: int = 1, max_items_per_instance: int = 0):
-    """Items grouped by template class (largest first) straight from the
+    """Items grouped by launch class (widest first) straight from the
     builder, with their segments: one launch per class."""
     items, per = build_queue(batch.k, cbits, lanes, cost=cost, order=order,
                              min_items_per_instance=min_items_per_instance,
@@ -494,7 +493,8 @@ class Sweeper:
         self.cap = cap
         self.surv = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=device)
         self.counts = torch.empty(max(1, len(batch.preps)), dtype=torch.int64, device=device)
-        self.total = torch.empty(2, dtype=torch.int64, device=device)  # [results, record slots]
+        # [results, record slots, malformed items skipped, 0]
+        self.total = torch.empty(L.TOTAL_WORDS, dtype=torch.int64, device=device)
         self.stats = torch.empty(8, dtype=torch.int64, device=device)
         self.scratch = torch.empty(4, dtype=torch.int64, device=device)
         self._items_dev = None
@@ -506,10 +506,10 @@ class Sweeper:
     def set_items(self, items: np.ndarray, want_times: bool = False,
                   bin_offsets: Optional[np.ndarray] = None, segments=None,
                   split_classes: bool = True):
-        """Upload the items.  By default items are grouped by kernel template
-        class and launched class by class; `segments` gives that grouping
+        """Upload the items.  By default items are grouped by launch class
+        and launched class by class; `segments` gives that grouping
         explicitly (packed plans carry per-segment bins); bin_offsets alone
-        means one packed launch under the batch-wide template."""
+        means one packed launch with the batch-wide LDS layout."""
         torch = self.torch
         if segments is None:
             if bin_offsets is not None or not split_classes:
@@ -526,7 +526,7 @@ class Sweeper:
                        if want_times else None)
 
     def launch(self, mode: int, wg_size: int = 256, grid: int = 0, stream=None,
-               seg_events: bool = False, accumulate: bool = False) -> None:
+               seg_events: bool = False, accumulate: bool = False, waves: int = 0) -> None:
         """One wpm_enumerate call per segment, in order, on `stream`.  With
         seg_events, HIP events bracket each segment's launch on that stream
         (self.seg_events: list of (class, start event, end event)).  With
@@ -551,7 +551,8 @@ class Sweeper:
                         h_items=items.ctypes.data + 16 * sg.start if n else None,
                         num_items=n, d_scratch=self.scratch.data_ptr(),
                         d_item_times=(self._times.data_ptr() + 16 * sg.start) if self._times is not None else None,
-                        d_bin_offsets=bins.data_ptr() if bins is not None else None)
+                        d_bin_offsets=bins.data_ptr() if bins is not None else None,
+                        waves_per_simd=waves)
             if mode == L.SCHED_PACKED:
                 if bins is None:
                     raise ValueError("packed mode needs per-segment bins")
@@ -565,7 +566,7 @@ class Sweeper:
                 self.seg_events.append((sg.cls, e0, e1))
 
     def launch_fetch(self, mode: int, wg_size: int = 256, grid: int = 0, stream=None,
-                     parts: int = 4, seg_events: bool = False):
+                     parts: int = 4, seg_events: bool = False, waves: int = 0):
         """Sweep and copy the survivor records to pinned host memory, with the
         copies overlapping the sweep: the largest segment is launched in
         `parts` consecutive item ranges, the record-slot counter is snapshot
@@ -610,7 +611,7 @@ class Sweeper:
                         h_items=items.ctypes.data + 16 * a0 if n else None,
                         num_items=n, d_scratch=self.scratch.data_ptr(),
                         d_item_times=(self._times.data_ptr() + 16 * a0) if self._times is not None else None,
-                        d_bin_offsets=None)
+                        d_bin_offsets=None, waves_per_simd=waves)
             if mode == L.SCHED_PACKED:  # never split: the bins cover the whole segment
                 bins = self._seg_bins[i] if self._segments else None
                 if bins is None:
@@ -666,6 +667,8 @@ class Sweeper:
         self.torch.cuda.synchronize()
         counts = self.counts[:len(self.batch.preps)].cpu().numpy().astype(np.uint64)
         tot = self.total.cpu().numpy()
+        if int(tot[2]):
+            raise L.WpmError(f"wpm_enumerate skipped {int(tot[2])} malformed items", L.WPM_EINVAL)
         return SweepResult(counts=counts, total=int(tot[0]), slots=int(tot[1]),
                            stats=self.stats.cpu().numpy(),
                            item_times=None if self._times is None else self._times.cpu().numpy(),

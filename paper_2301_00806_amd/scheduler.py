@@ -54,8 +54,9 @@ def _items(batch, split: bool, cbits: int, wg: int, cost=None, order: int = 0,
 def make_plan(batch: "E.DeviceBatch", policy: str, cost: Optional[np.ndarray] = None,
               cbits: int = 16, wg: int = 256, plain_min_items: int = 512,
               split: bool = True) -> Plan:
-    """Items for a policy; with `split`, grouped by kernel template class
-    (one launch per class), else one launch under the batch's largest template."""
+    """Items for a policy; with `split`, grouped by launch class (one launch
+    per class, each with the LDS layout its tables need), else one launch for
+    the whole batch."""
     if policy == "plain":
         items, segs = _items(batch, split, cbits, wg, min_items=plain_min_items)
         return Plan(policy, L.SCHED_PLAIN, items, segs)
@@ -89,7 +90,7 @@ def measure_labels(preps, cbits: int = 12, wg: int = 256, repeats: int = 2):
     items = E.build_queue(batch.k, cbits, wg, cost=np.ones(len(preps), np.float32), order=1,
                           blocks=batch.blocks)
     sw.set_items(items, want_times=True)
-    items = sw._items_host  # grouped by template class, as launched
+    items = sw._items_host  # grouped by launch class, as launched
     sw.launch(L.SCHED_DYNAMIC, wg_size=wg)
     sw.result()
     labs = []

@@ -1,10 +1,12 @@
-"""Autotuner for the persistent sweep: lane chunk bits and workgroup size.
+"""Autotuner for the persistent sweep: lane chunk bits, workgroup size and
+the kernel's register budget (7 or 8 waves per SIMD).
 
 It times candidate launch shapes on a sample of the batch (the instances that
 hold most of the work, plus a spread of small ones), keeps the fastest, and
-caches the choice in a JSON file keyed by the GPU architecture and a shape
-bucket of the batch (kernel template class and log2 of the vectors per
-instance).  Counts are identical for every shape; the tuner checks that too.
+caches the choice in a JSON file keyed by the GPU architecture, the kernel
+source and a shape bucket of the batch (widest table row, log2 of the vectors
+per instance, pruned or not).  Counts are identical for every shape; the
+tuner checks that too.
 """
 from __future__ import annotations
 
@@ -19,19 +21,22 @@ from . import _lib as L
 from . import engine as E
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "wpm_tune.json")
-CBITS = (12, 14, 16, 18)
+CBITS = (10, 11, 12, 13, 14, 16)
 WGS = (128, 256)
+WAVES = (7, 8)
 
 
 def shape_key(batch: "E.DeviceBatch") -> str:
+    import hashlib
     import torch
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     b = batch.c_batch
-    gm = 2 if b.max_groups <= 2 else 4 if b.max_groups <= 4 else 8 if b.max_groups <= 8 else 16
-    wm = 4 if b.max_words <= 4 else 10 if b.max_words <= 10 else 16 if b.max_words <= 16 else 32
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "sweep_kernel.h")
+    with open(src, "rb") as f:
+        kh = hashlib.sha256(f.read()).hexdigest()[:12]
     lv = int(np.log2(max(1.0, batch.visited / max(1, len(batch.preps)))))
     pr = "/pruned" if batch.blocks is not None else ""
-    return f"{arch}/gm{gm}/qs{b.max_slots}/wm{wm}/v{lv}{pr}"
+    return f"{arch}/{kh}/rs{b.max_row_words}/v{lv}{pr}"
 
 
 def _sample(preps, budget_vectors: float):
@@ -50,7 +55,7 @@ def _sample(preps, budget_vectors: float):
 
 
 def tune(preps: Sequence, cache: Optional[str] = DEFAULT_CACHE, budget_vectors: float = 2e11,
-         cbits=CBITS, wgs=WGS, repeats: int = 2, force: bool = False, log=None) -> Dict:
+         cbits=CBITS, wgs=WGS, waves=WAVES, repeats: int = 2, force: bool = False, log=None) -> Dict:
     import torch
     full = E.DeviceBatch(preps)
     key = shape_key(full)
@@ -74,26 +79,29 @@ def tune(preps: Sequence, cache: Optional[str] = DEFAULT_CACHE, budget_vectors: 
             items = E.build_queue(batch.k, cb, wg, cost=np.ones(len(sub), np.float32), order=1,
                                   blocks=batch.blocks)
             sw.set_items(items)
-            sw.launch(L.SCHED_DYNAMIC, wg_size=wg)
-            r = sw.result()
-            if ref is None:
-                ref = r.counts.copy()
-            if not np.array_equal(r.counts, ref):
-                raise RuntimeError(f"counts changed with cbits={cb} wg={wg}")
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(repeats):
-                sw.launch(L.SCHED_DYNAMIC, wg_size=wg)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / repeats
-            results.append({"cbits": cb, "wg": wg, "ms": ms, "vectors_per_s": vec / ms * 1e3})
-            if log:
-                log(f"tune cbits={cb} wg={wg}: {ms:.2f} ms ({vec / ms * 1e3:.3e} vectors/s)")
+            for wv in waves:
+                sw.launch(L.SCHED_DYNAMIC, wg_size=wg, waves=wv)
+                r = sw.result()
+                if ref is None:
+                    ref = r.counts.copy()
+                if not np.array_equal(r.counts, ref):
+                    raise RuntimeError(f"counts changed with cbits={cb} wg={wg} waves={wv}")
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(repeats):
+                    sw.launch(L.SCHED_DYNAMIC, wg_size=wg, waves=wv)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / repeats
+                results.append({"cbits": cb, "wg": wg, "waves": wv, "ms": ms,
+                                "vectors_per_s": vec / ms * 1e3})
+                if log:
+                    log(f"tune cbits={cb} wg={wg} waves={wv}: {ms:.2f} ms ({vec / ms * 1e3:.3e} vectors/s)")
     best = max(results, key=lambda r: r["vectors_per_s"])
-    entry = {"cbits": best["cbits"], "wg": best["wg"], "sample_instances": len(sub),
-             "sample_vectors": vec, "results": results, "when": time.time()}
+    entry = {"cbits": best["cbits"], "wg": best["wg"], "waves": best["waves"],
+             "sample_instances": len(sub), "sample_vectors": vec, "results": results,
+             "when": time.time()}
     if cache:
         os.makedirs(os.path.dirname(cache), exist_ok=True)
         db[key] = entry

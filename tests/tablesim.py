@@ -3,9 +3,10 @@
 It evaluates, for every kernel vector x of a small instance, the same
 predicate the GPU sweep evaluates from the table: the bit-sliced ridge slots
 (at least 3 of a ridge's slot bits set = the ridge has degree 4), the facet
-count bound and x != 0.  It also replays the kernel's two-phase walk over Gray
-blocks (incremental fast-filter state, per-block base P, low-part table T) so
-the walk's bookkeeping is checked without a GPU.
+count bound and x != 0.  It also replays the kernel's walk over Gray
+blocks (incremental fast-filter state; each candidate's full state rebuilt
+from the item's reference state, lane tables, segment rows and the Gray-bit
+tables) so the walk's bookkeeping is checked without a GPU.
 """
 import numpy as np
 
@@ -119,55 +120,103 @@ def survivors_direct(tab):
     return sorted(x for x in range(first, 1 << h["k"]) if accept(h, state(R, x) ^ off))
 
 
-def survivors_walk(tab, cbits=7):
-    """Replays the GPU walk: lanes = chunks of 2^cbits Gray indices.
+LANE_BITS = 9  # an item's lane chunks lie in one aligned window of 2^9 chunks
 
-    The fast filter follows the 4 group-0 words step by step.  P, the full
-    state, is the lane's state at the start of the current 4096-step segment:
-    a passing step r of the chunk is rebuilt as P ^ S(gray(r) mod 2^12) from
-    four 8-row tables of the Gray bits 0-2, 3-5, 6-8 and 9-11, because
-    gray(i0 + r) = gray(i0) ^ gray(r) for a 2^c-aligned i0, and bit 12 of r
-    (the segment parity) toggles Gray bit 11.
+
+def _xor_rows(R, kp, first_row, v, nbits):
+    """XOR of the rows first_row + j over the set bits j < nbits of v (rows
+    >= kp count as zero)."""
+    out = np.zeros(R.shape[1], dtype=np.uint64)
+    for j in range(nbits):
+        if (v >> j) & 1 and first_row + j < kp:
+            out ^= R[first_row + j]
+    return out
+
+
+def survivors_walk(tab, cbits=7, lanes=64, offset_first=0):
+    """Replays the GPU walk: items of `lanes` consecutive chunks of 2^cbits
+    Gray indices, the item's first chunk a multiple of `lanes` (plus
+    offset_first, to exercise unaligned windows).
+
+    The fast filter follows the 4 group-0 words step by step.  A passing step
+    r of segment sg of lane l is rebuilt from tables alone, as the kernel's
+    check does: x = gray(i) for i = ((ref + d) << c) + (sg << 12) + r, with
+    ref the item's first chunk rounded down to a multiple of 2^LANE_BITS and
+    d = the lane's offset from it; by linearity of the Gray code its state is
+      Ref                 rows of gray(ref << c) (the offset row included)
+      ^ Lane(d)           rows c - 1 + i over the bits i of d ^ (d << 1),
+                          from four tables of bits 0-2, 3-5, 6-8, 9
+      ^ Seg(sg)           rows 12 + j over the bits j of gray(sg)
+      ^ S(g12)            rows of the Gray bits 0-11 of r, bit 11 toggled by
+                          the segment parity, from four tables of 3 bits.
+    Every rebuilt state is compared with the direct sum of the rows of x.
     """
     h = header(tab)
     R = rows(tab)
+    off = offset_row(tab)
+    h["props"] = properties(tab)
+    h["deferred"] = deferred(tab)
     kp, k = h["kp"], h["k"]
     c = min(max(cbits, 7), kp)
-    # T[b][v]: XOR of the rows 3b + j over the set bits j of v (rows >= kp are zero)
     T = np.zeros((4, 8, R.shape[1]), dtype=np.uint64)
     for b in range(4):
         for v in range(8):
-            T[b][v] = state(R[3 * b:min(3 * b + 3, kp)], v & ((1 << max(0, min(3, kp - 3 * b))) - 1))
+            T[b][v] = _xor_rows(R, kp, 3 * b, v, 3)
+    chunks = 1 << (kp - c)
     out = []
-    for j in range(1 << (kp - c)):
-        i0 = j << c
-        x0 = i0 ^ (i0 >> 1)
-        P = state(R, x0)
-        s4 = P[:4].copy()
-        nblk = 1 << (c - 6)
-        for blk in range(nblk):
-            cand = []
-            for s in range(64):
-                if at_least3(slots4(s4, 0)) == 0:
-                    cand.append(s)
-                if s < 63:
-                    t = (s + 1 & -(s + 1)).bit_length() - 1
+    first = 0
+    items = []
+    while first < chunks:
+        f = min(chunks, first + offset_first) if first == 0 and offset_first else first
+        n = min(lanes, chunks - f)
+        if first == 0 and offset_first:
+            items.append((0, min(chunks, offset_first)))
+        items.append((f, n))
+        first = f + n
+    for first, n in items:
+        if n <= 0:
+            continue
+        ref = first & ~((1 << LANE_BITS) - 1)
+        assert (first - ref) + n <= (1 << LANE_BITS), "lane window crosses an aligned group"
+        iref = ref << c
+        xref = iref ^ (iref >> 1)
+        Ref = off.copy()
+        for t in range(kp):
+            if (xref >> t) & 1:
+                Ref ^= R[t]
+        L = [[_xor_rows(R, kp, c - 1 + 3 * b, v, 3 if b < 3 else 1) for v in range(8)] for b in range(4)]
+        for l in range(n):
+            d = (first - ref) + l
+            g = d ^ (d << 1)
+            lane = Ref ^ L[0][g & 7] ^ L[1][(g >> 3) & 7] ^ L[2][(g >> 6) & 7] ^ L[3][(g >> 9) & 1]
+            i0 = (first + l) << c
+            s4 = lane[:4].copy()
+            seg_row = np.zeros(R.shape[1], dtype=np.uint64)
+            nblk = 1 << (c - 6)
+            for blk in range(nblk):
+                cand = []
+                for s in range(64):
+                    if at_least3(slots4(s4, 0)) == 0:
+                        cand.append(s)
+                    if s < 63:
+                        t = (s + 1 & -(s + 1)).bit_length() - 1
+                        s4 ^= R[t, :4]
+                seg = blk >> 6
+                for s in cand:
+                    r12 = ((blk & 63) << 6) | s
+                    g12 = (r12 ^ (r12 >> 1)) ^ ((seg & 1) << 11)
+                    v = (lane ^ seg_row ^ T[0][g12 & 7] ^ T[1][(g12 >> 3) & 7] ^ T[2][(g12 >> 6) & 7]
+                         ^ T[3][g12 >> 9])
+                    i = i0 + (seg << 12) + r12
+                    x = i ^ (i >> 1)
+                    assert np.array_equal(v, state(R, x) ^ off), (first, l, blk, s)
+                    if (x or h["offset"]) and (x >> k) == 0 and accept(h, v):
+                        out.append(x)
+                if blk + 1 < nblk:
+                    t = 6 + ((blk + 1) & -(blk + 1)).bit_length() - 1
+                    if t >= 12:
+                        seg_row ^= R[t]
                     s4 ^= R[t, :4]
-            seg = blk >> 6
-            for s in cand:
-                r12 = ((blk & 63) << 6) | s
-                g12 = (r12 ^ (r12 >> 1)) ^ ((seg & 1) << 11)
-                v = P ^ T[0][g12 & 7] ^ T[1][(g12 >> 3) & 7] ^ T[2][(g12 >> 6) & 7] ^ T[3][g12 >> 9]
-                i = i0 + (seg << 12) + r12
-                x = i ^ (i >> 1)
-                assert np.array_equal(v, state(R, x))
-                if x and (x >> k) == 0 and accept(h, v):
-                    out.append(x)
-            if blk + 1 < nblk:
-                t = 6 + ((blk + 1) & -(blk + 1)).bit_length() - 1
-                if t >= 12:
-                    P ^= R[t]
-                s4 ^= R[t, :4]
     return sorted(out)
 
 

@@ -1,9 +1,9 @@
 """Parity at the benchmark's full size, in the launch configuration bench.py
 times: the 16384-instance learned-scheduler batch, one persistent launch per
-kernel template class, dynamic queue, 12 chunk bits, 256-thread workgroups.
+launch class, dynamic queue, 12 chunk bits, 256-thread workgroups.
 
   - the count of every instance equals the oracle's (golden/learned16384_counts.json,
-    written by golden/make_learned_counts.py from the oracle alone);
+    written by golden/make_counts.py from the oracle alone);
   - every instance with 1 <= k <= 10, and a sample across every larger k (up to
     the k = 34 maximum of the batch), compared set for set with the oracle;
   - a random sample of survivor records, from all instances, checked by the
@@ -22,6 +22,7 @@ import pytest
 
 import oracle as O
 import wpm_inputs as W
+from setcheck import kvec, kvec_of_sets, canon, facet_list
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -33,36 +34,6 @@ def golden_counts():
     with open(os.path.join(os.path.dirname(__file__), "golden", "learned16384_counts.json")) as f:
         g = json.load(f)
     return np.array(g["counts"], dtype=np.uint64)
-
-
-def kvec(p, xs):
-    """Facet bit vectors K = sum_t x_t K_t (rows of W uint32) of kernel vectors x."""
-    xs = np.asarray(xs, dtype=np.uint64)
-    K = np.zeros((len(xs), p.W), dtype=np.uint32)
-    for t in range(p.k):
-        sel = ((xs >> np.uint64(t)) & np.uint64(1)).astype(bool)
-        K[sel] ^= p.basis[t]
-    return K
-
-
-def kvec_of_sets(p, sets):
-    """The same bit vectors for lists of facet masks (the oracle's output)."""
-    pos = {int(f): j for j, f in enumerate(p.facets)}
-    K = np.zeros((len(sets), p.W), dtype=np.uint32)
-    for r, S in enumerate(sets):
-        for f in S:
-            j = pos[f]
-            K[r, j // 32] |= np.uint32(1 << (j % 32))
-    return K
-
-
-def canon(K):
-    return K[np.lexsort(K.T[::-1])] if len(K) else K
-
-
-def facet_list(p, x):
-    K = kvec(p, [x])[0]
-    return [int(p.facets[w * 32 + b]) for w in range(p.W) for b in range(32) if (int(K[w]) >> b) & 1]
 
 
 @pytest.fixture(scope="module")
@@ -102,7 +73,7 @@ def test_sets_match_oracle_small_and_sampled(run):
     ks = np.array([p.k for p in preps])
     rng = np.random.default_rng(11)
     chosen = list(np.flatnonzero((ks >= 1) & (ks <= 10)))
-    for k in sorted(set(ks[ks > 14])):
+    for k in sorted(set(ks[ks > 10])):
         idx = np.flatnonzero(ks == k)
         chosen += list(rng.choice(idx, size=min(3, len(idx)), replace=False))
     print(f"[fullsize] oracle on {len(chosen)} instances", flush=True)

@@ -63,9 +63,9 @@ def test_single_n6_m10(E):
 
 
 def test_single_chunks_across_segments(E):
-    # 2^14-step chunks: each lane's state P changes at the 4096-step segment
-    # boundaries inside its chunk, and candidates of odd segments use Gray
-    # bit 11 toggled by the segment parity
+    # 2^14-step chunks: each wave's segment row changes at the 4096-step
+    # segment boundaries inside its chunks, and candidates of odd segments use
+    # Gray bit 11 toggled by the segment parity
     inst = W.single(E.kdim)
     p = E.prepare(inst.n, inst.m, lam=inst.lam)
     res, sets = run(E, [p], cbits=14, wg_size=64)
@@ -186,9 +186,9 @@ def test_stress_large_k_outputs_verified(E):
         assert s == want
 
 
-def test_deferred_ridges_verification_pass(E):
-    # one or two resident groups: the other critical ridges are checked on
-    # the survivor records by the verification pass, counts stay exact
+def test_deferred_ridges_checked_in_the_sweep(E):
+    # one or two resident groups: the other critical ridges are checked by
+    # the sweep itself before a vector is counted, so counts stay exact
     insts = [i for i in W.batch(E.kdim, count=64) if 14 <= i.meta["k"] <= 22][:12]
     preps = [E.prepare(i.n, i.m, lam=i.lam, max_groups=1 + (j % 2)) for j, i in enumerate(insts)]
     for v in (7, 8):
@@ -196,10 +196,93 @@ def test_deferred_ridges_verification_pass(E):
         preps.append(E.prepare(2, v, facets=F, max_facets=0, max_groups=1))
     assert sum(p.info.n_deferred for p in preps) > 0
     want = oracle_sets(preps)
-    # with one resident group every vector of K_8 is a candidate (its ridges
-    # have 7 parents, too many for the filter): records before verification
-    # exceed the default buffer
     for mode, cbits in ((2, 9), (0, 7)):
-        res, sets = run(E, preps, mode=mode, cbits=cbits, cap=1 << 24)
+        res, sets = run(E, preps, mode=mode, cbits=cbits, cap=1 << 22)
         assert sets == want
         assert list(res.counts) == [len(w) for w in want] and res.total == sum(len(w) for w in want)
+
+
+def test_deferred_ridges_exact_counts_after_record_overflow(E):
+    # a record buffer of 64 slots and a single resident group: most records
+    # are lost, yet every count equals the oracle's (deferred ridges are
+    # checked before counting), and collect reports the overflow
+    from paper_2301_00806_amd import _lib as L
+    insts = [i for i in W.batch(E.kdim, count=64) if 14 <= i.meta["k"] <= 20 and i.n >= 6][:6]
+    preps = [E.prepare(i.n, i.m, lam=i.lam, max_groups=1) for i in insts]
+    F = [(1 << a) | (1 << b) for a, b in itertools.combinations(range(8), 2)]
+    preps.append(E.prepare(2, 8, facets=F, max_facets=0, max_groups=1))
+    assert all(p.info.n_deferred > 0 for p in preps)
+    want = [O.count_wpm(p.n, [int(f) for f in p.facets], p.max_facets) for p in preps]
+    batch = E.DeviceBatch(preps)
+    sw = E.Sweeper(batch, cap=64)
+    sw.set_items(E.build_queue(batch.k, 8, 64))
+    _say(f"[gpu] deferred ridges, cap 64: {len(preps)} instances")
+    sw.launch(2, wg_size=64)
+    res = sw.result()
+    assert res.slots > 64
+    assert [int(c) for c in res.counts] == want and res.total == sum(want)
+    with pytest.raises(L.WpmError) as ei:
+        sw.collect()
+    assert ei.value.status == L.WPM_ECAP
+
+
+def test_mixed_slot_strides_in_one_launch(E):
+    # instances packed with 4 slot words per ridge (the batch workload) and
+    # with 8 (complete graphs: ridges of 6 and 7 parents), swept together in
+    # one launch: every table is read with its own stride
+    insts = [i for i in W.batch(E.kdim, count=48) if i.meta["k"] <= 20][:10]
+    preps = E.prepare_many(insts)
+    for v in (7, 8):
+        F = [(1 << a) | (1 << b) for a, b in itertools.combinations(range(v), 2)]
+        preps.append(E.prepare(2, v, facets=F, max_facets=0))
+    assert {p.info.slots for p in preps} == {4, 8}
+    batch = E.DeviceBatch(preps)
+    sw = E.Sweeper(batch, cap=1 << 22)
+    sw.set_items(E.build_queue(batch.k, 9, 256), split_classes=False)
+    _say(f"[gpu] mixed strides, one launch: {len(preps)} instances")
+    sw.launch(2, wg_size=256)
+    sw.result()
+    assert sw.collect() == oracle_sets(preps)
+
+
+@pytest.mark.parametrize("waves", [7, 8])
+def test_both_register_budgets(E, waves):
+    insts = [i for i in W.batch(E.kdim, count=96) if i.meta["k"] <= 22][:24]
+    preps = E.prepare_many(insts)
+    batch = E.DeviceBatch(preps)
+    sw = E.Sweeper(batch, cap=1 << 22)
+    sw.set_items(E.build_queue(batch.k, 13, 128))
+    _say(f"[gpu] {waves} waves per SIMD: {len(preps)} instances")
+    sw.launch(2, wg_size=128, waves=waves)
+    sw.result()
+    assert sw.collect() == oracle_sets(preps)
+
+
+def test_malformed_items_are_skipped_and_reported(E):
+    # items the kernel must refuse: chunk bits below 7, a lane window that
+    # crosses an aligned group of 512 chunks, chunks beyond 2^k, an unknown
+    # instance; each is skipped and counted, and the valid items still run
+    from paper_2301_00806_amd import _lib as L
+    insts = [i for i in W.batch(E.kdim, count=32) if i.meta["k"] <= 16][:2]
+    preps = E.prepare_many(insts)
+    batch = E.DeviceBatch(preps)
+    good = E.build_queue(batch.k, 7, 64)
+    bad = np.zeros(4, dtype=E.ITEM_DTYPE)
+    bad[0] = (0, 5, 64, 0)                                   # cbits < 7
+    bad[1] = (0, 7, 64, 480)                                 # 480 + 64 > 512
+    bad[2] = (1, 7, 64, (1 << (max(preps[1].k, 7) - 7)))     # beyond 2^k
+    bad[3] = (len(preps), 7, 64, 0)                          # unknown instance
+    items = np.concatenate([good, bad])
+    sw = E.Sweeper(batch, cap=1 << 20)
+    sw.set_items(items, split_classes=False)
+    _say("[gpu] malformed items")
+    sw.launch(2, wg_size=64)
+    torch.cuda.synchronize()
+    tot = sw.total.cpu().numpy()
+    assert int(tot[2]) == 4
+    assert [int(c) for c in sw.counts[:2].cpu().numpy()] == [len(s) for s in oracle_sets(preps)]
+    with pytest.raises(L.WpmError):
+        sw.result()
+    with pytest.raises(L.WpmError) as ei:
+        sw.collect()
+    assert ei.value.status == L.WPM_EINVAL

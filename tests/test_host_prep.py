@@ -90,12 +90,26 @@ def test_walk_with_larger_chunks():
 
 
 def test_walk_across_4096_step_segments():
-    # chunks of 2^13 steps: P changes once inside each chunk (t = 12), and
-    # the second segment's candidates use Gray bit 11 toggled by its parity
+    # chunks of 2^13 steps: the segment row takes row 12 once inside each
+    # chunk, and the second segment's candidates use Gray bit 11 toggled by
+    # its parity
     inst = [i for i in W.batch(O.kdim_of, count=64) if 14 <= i.meta["k"] <= 15][0]
     p = E.prepare(inst.n, inst.m, lam=inst.lam)
     assert p.k >= 14
     assert TS.survivors_walk(p.table, cbits=13) == TS.survivors_direct(p.table)
+
+
+def test_walk_with_unaligned_items_and_coset():
+    # items whose first chunk is not a multiple of their lane count (the lane
+    # offset from the item's aligned reference is then nonzero), in a coset
+    # (the offset row is part of the reference state)
+    inst = [i for i in W.batch(O.kdim_of, count=64) if 14 <= i.meta["k"] <= 16][0]
+    p = E.prepare(inst.n, inst.m, lam=inst.lam)
+    assert TS.survivors_walk(p.table, cbits=7, lanes=48, offset_first=5) == TS.survivors_direct(p.table)
+    K = TS.facets_of_x(p.basis, p.facets, TS.survivors_direct(p.table)[0])
+    q = E.prepare(inst.n, inst.m, lam=inst.lam, forced_in=[K[0]])
+    assert q.offset is not None and q.k >= 8
+    assert TS.survivors_walk(q.table, cbits=7, lanes=64, offset_first=3) == TS.survivors_direct(q.table)
 
 
 def test_pack_rejects_large_k_and_bad_input():
@@ -169,7 +183,7 @@ def test_single_hip_runtime_in_process():
     assert len(hips) == 1, hips
 
 
-def test_template_class_split_keeps_every_item():
+def test_launch_class_split_keeps_every_item():
     k = np.array([7, 12, 16, 9, 20], dtype=np.int32)
     items = E.build_queue(k, 9, 64)
 

@@ -1,0 +1,90 @@
+"""Direct paper pins of the filter and orbit oracles (oracle/seeds.py,
+oracle/idcm.py): each number here is computed by oracle code alone, with no
+engine call, and compared with a value the paper prints.
+
+  - Table 1 (Section 4.2), the row of IDCM orbit counts of Lambda(n, 4):
+    the orbit representatives that oracle/idcm.py finds by trying every row
+    subset and every coordinate permutation, for n = 2..11.
+  - Table 1, the row "max dim ker A(F(lambda))" over the IDCMs: the oracle's
+    candidates and F2 rank on each of oracle/idcm.py's representatives.
+  - Table 2 (Section 4.2), the third row (isomorphism classes of seeds of
+    Picard number 4 supporting an IDCM) for n = 2 and n = 3: Algorithm 4.4
+    up to its isomorphism step, run entirely on the oracle -- orbit
+    representatives, the backtracking enumeration with the upper-bound
+    property, the union over the orbits, Pic(K) = 4 and seedness
+    (oracle/seeds.py), and the classes of oracle/seeds.py's exhaustive
+    canonical form.
+"""
+import json
+import os
+
+import pytest
+
+import oracle as O
+from oracle import idcm as OI
+from oracle import seeds as OS
+
+TABLE2_CLASSES = {2: 2, 3: 5}
+
+
+def _table1():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table1.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("n", list(range(2, 12)))
+def test_oracle_orbit_counts_match_table1(n):
+    t = _table1()
+    assert len(OI.orbit_representatives(n)) == t["idcm_orbits"][t["n"].index(n)]
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_oracle_max_kernel_dimension_over_orbits_matches_table1(n):
+    t = _table1()
+    m = n + 4
+    ks = [O.kernel_dim(n, O.candidates(n, m, OI.lambda_of(rows))) for rows in OI.orbit_representatives(n)]
+    assert max(ks) == t["max_dim_ker_idcm"][t["n"].index(n)]
+
+
+def _oracle_union(n):
+    """K(n, 4): the union over the orbit representatives of every weak
+    pseudo-manifold with facets in F(lambda) and at most f(n) facets."""
+    m = n + 4
+    out = set()
+    for rows in OI.orbit_representatives(n):
+        F = O.candidates(n, m, OI.lambda_of(rows))
+        out |= {tuple(sorted(K)) for K in O.enumerate_wpm(n, F, O.ubt_bound(n))}
+    return sorted(out)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_oracle_pipeline_reproduces_table2_classes(n):
+    m = n + 4
+    U = _oracle_union(n)
+    kept = [K for K in U if OS.picard(K, n) == m - n and OS.is_seed(K, m)]
+    classes = {OS.canonical_form(K, m) for K in kept}
+    assert len(classes) == TABLE2_CLASSES[n]
+
+
+def test_oracle_filters_on_known_complexes():
+    """Hand-checkable cases of the definitions themselves.
+    The boundary of the triangle on {0,1,2} (n = 2, m = 3): Picard number 1,
+    its only minimal non-face is {0,1,2}, which contains every edge, so the
+    seedness condition fails.  The boundary of the square 0-1-2-3 (n = 2,
+    m = 4): minimal non-faces {0,2} and {1,3}; no edge lies in or avoids both,
+    so it is a seed; its Picard number is 2."""
+    tri = [0b011, 0b110, 0b101]
+    assert OS.picard(tri, 2) == 1
+    assert OS.minimal_nonfaces(tri, 3) == [0b111]
+    assert not OS.is_seed(tri, 3)
+    sq = [0b0011, 0b0110, 0b1100, 0b1001]
+    assert sorted(OS.minimal_nonfaces(sq, 4)) == [0b0101, 0b1010]
+    assert OS.picard(sq, 2) == 2
+    assert OS.is_seed(sq, 4)
+    # two labellings of the hexagon share the canonical form; the hexagon and
+    # two disjoint triangles on the same 6 vertices do not
+    hexa = [(1 << i) | (1 << ((i + 1) % 6)) for i in range(6)]
+    hexb = [(1 << a) | (1 << b) for a, b in [(0, 3), (3, 1), (1, 4), (4, 2), (2, 5), (5, 0)]]
+    two_tri = [0b000011, 0b000110, 0b000101, 0b011000, 0b110000, 0b101000]
+    assert OS.canonical_form(hexa, 6) == OS.canonical_form(hexb, 6)
+    assert OS.canonical_form(hexa, 6) != OS.canonical_form(two_tri, 6)
