@@ -35,7 +35,9 @@ def log(msg: str) -> None:
 # every 2 clocks on each of 4 SIMDs, the same issue rate as fp32 FMA behind the
 # 157.3 TFLOP/s figure) x 2.4 GHz.  wpm_valu_probe measures it on the device.
 INT32_PEAK = 256 * 128 * 2.4e9
-ALG_OPS_PER_VECTOR = 7             # fast filter: 4 XOR + 2 threshold ops + 1 compare
+# Fast filter per kernel vector: 4 XORs and 2 threshold ops, plus a 3-input
+# minimum, a minimum and a compare shared by the four chains of a step.
+ALG_OPS_PER_VECTOR = 4 + 2 + 3 / 4
 
 
 def ops_alg_plain(p) -> int:
@@ -453,7 +455,7 @@ def main():
                      "vectors_per_launch": cls_vec[dom], "ops_per_vector": ALG_OPS_PER_VECTOR,
                      "ops_alg_plain_per_vector": plain_per_vec,
                      "effective_plain": effective, "effective_plain_frac": effective / (INT32_PEAK / 1e12),
-                     "note": "frac prices a vector at the fast filter's 7 int32 ops; effective_plain prices it "
+                     "note": "frac prices a vector at the fast filter's 6.75 int32 ops; effective_plain prices it "
                              "at the plain per-ridge AND+popcount check of the same launch (saved work, "
                              "not skipped work: every count equals the oracle's)",
                      "measured_int32_xor_peak": probe / 1e12,

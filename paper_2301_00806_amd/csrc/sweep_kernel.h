@@ -6,15 +6,17 @@
 // (Section 2.1: the weak pseudo-manifolds are among the 2^k combinations of a
 // kernel basis).  Chunks are 2^c-aligned with c >= 7, so all lanes of a
 // workgroup flip the same t at the same step: the XOR operands are
-// wave-uniform and live in SGPRs.
+// wave-uniform.  They are held in VGPRs all the same: a VOP2 XOR with a
+// scalar operand issues markedly slower than one with two VGPR operands.
 //
 // A step checks the ridges whose parents Proposition 2.1 constrains, in the
 // bit-sliced slot form built by the packer (a ridge fails iff at least 3 of
 // its first p-1 parent bits are set).  Work per block of 64 steps:
 //   phase 1  the fast filter: 32 ridges in 4 slot words held in VGPRs,
 //            updated by 4 XORs and tested by 2 bit-logic ops per step, the
-//            two halves of the block as interleaved chains.  When a lane
-//            passes (a rarely taken branch), the passing lanes append
+//            block run as four interleaved chains of 16 steps whose fail
+//            words one 3-input minimum and one compare test together.  When
+//            a lane passes (a rarely taken branch), the passing lanes append
 //            (step, lane) to the wave's candidate list in LDS; ballot and
 //            mbcnt give the slots, the count is wave-uniform.
 //   check    when the list is half full, at the end of a 4096-step segment
@@ -94,10 +96,7 @@ struct KArgs {
 // stored words a, u = a^b, c, v = c^d.  Counting a + b = 2a when u = 0 and 1
 // when u = 1 (likewise for c, d), the test is (u | a) & ~(u & v) & (v | c):
 // two 3-input logic ops (v_bitop3; operand i is truth-table input 0xF0, 0xCC,
-// 0xAA for i = 0, 1, 2).  The test is symmetric in the pairs (a, u) and
-// (c, v); which pair the second op reads decides whether its three operands
-// sit in three VGPR banks under the compiler's allocation (a shared bank
-// costs issue cycles), and this order gives distinct banks in the sweep loop.
+// 0xAA for i = 0, 1, 2).
 __device__ __forceinline__ uint32_t fail4(uint32_t a, uint32_t u, uint32_t c, uint32_t v) {
     const uint32_t t = __builtin_amdgcn_bitop3_b32(u, a, v, 0x5C);  // (u | a) & ~(u & v)
     return __builtin_amdgcn_bitop3_b32(t, v, c, 0xE0);                // t & (v | c)
@@ -119,14 +118,14 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
 //   [32][RS]         Gray-bit tables of the staged instance (steps' bits 0-11)
 //   [26][RS]         lane tables of the current item (Ref in rows 0-7)
 //   [nw][RS]         per-wave segment rows
-//   [RS]             the item's reference state (set-up only)
 //   [kp][4]          the phase-1 words of every basis row (block boundaries)
+constexpr int PH1_CHAINS = 4;  // interleaved chains of the fast filter
 constexpr int LIST_CAP = 256;   // candidates a wave's list holds
 constexpr int LIST_FLUSH = 128; // a block ending with at least this many checks them
 __host__ __device__ constexpr size_t sweep_lds_bytes(int max_kp, int max_row_words, int wg_size) {
     return sizeof(uint32_t) *
            ((size_t)(wg_size / 64) * LIST_CAP + (size_t)4 * wg_size +
-            (size_t)(GRAY_ROWS + LANE_ROWS + wg_size / 64 + 1) * (size_t)max_row_words +
+            (size_t)(GRAY_ROWS + LANE_ROWS + wg_size / 64) * (size_t)max_row_words +
             (size_t)4 * (size_t)max_kp);
 }
 
@@ -245,56 +244,56 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
         const uint32_t *__restrict__ rows = tab + DEV_HDR_WORDS;
         uint32_t *const lds_L = lds_T + GRAY_ROWS * RS;      // [26][RS]
         uint32_t *const lds_seg = lds_L + LANE_ROWS * RS;    // [nw][RS]
-        uint32_t *const lds_ref = lds_seg + nw * RS;         // [RS]
-        uint32_t *const lds_R4 = lds_ref + RS;               // [kp][4]
+        uint32_t *const lds_R4 = lds_seg + nw * RS;          // [kp][4]
 
         // ---- set-up of the staged instance: Gray-bit tables (row v of
         // table b = XOR of the basis rows 3b + j over the set bits j of v;
-        // rows >= kp count as zero) and the phase-1 words of every row
+        // rows >= kp count as zero) and the phase-1 words of every row.  A
+        // thread takes one word of one table: its three row words are loaded
+        // together, then the 8 rows are written.
         if ((int64_t)inst != staged) {
-            for (int e = tid_now(); e < GRAY_ROWS * RS; e += bd) {
-                const int v = e / RS, w = e - v * RS;
-                const int t0 = 3 * (v >> 3);
-                uint32_t acc = 0;
-                for (int t = 0; t < 3; ++t)
-                    if (((v >> t) & 1) && t0 + t < kp) acc ^= rows[(t0 + t) * RS + w];
-                lds_T[e] = acc;
+            for (int e = tid_now(); e < 4 * RS; e += bd) {
+                const int b = e / RS, w = e - b * RS;
+                const int t0 = 3 * b;
+                const uint32_t r0 = t0 < kp ? rows[t0 * RS + w] : 0u;
+                const uint32_t r1 = t0 + 1 < kp ? rows[(t0 + 1) * RS + w] : 0u;
+                const uint32_t r2 = t0 + 2 < kp ? rows[(t0 + 2) * RS + w] : 0u;
+                uint32_t *dst = lds_T + (8 * b) * RS + w;
+#pragma unroll
+                for (int v = 0; v < 8; ++v)
+                    dst[v * RS] = ((v & 1) ? r0 : 0u) ^ ((v & 2) ? r1 : 0u) ^ ((v & 4) ? r2 : 0u);
             }
             for (int e = tid_now(); e < 4 * kp; e += bd) lds_R4[e] = rows[(e >> 2) * RS + (e & 3)];
             staged = inst;
         }
         // ---- set-up of the item: the reference index is the first chunk
         // rounded down to a multiple of 2^LANE_BITS; Ref = offset + the rows
-        // of its Gray bits (all at or above c + LANE_BITS - 1)
+        // of its Gray bits (all at or above c + LANE_BITS - 1).  Lane table
+        // b, row v: the rows c - 1 + 3b + j over the set bits j of v (rows >=
+        // kp count as zero), with Ref added to every row of table 0.  A
+        // thread takes one word of one table, as above; the rows of Ref are
+        // loaded unconditionally and masked, so their loads are independent.
         const uint64_t ref = first & ~(uint64_t)((1u << LANE_BITS) - 1);
         const uint64_t iref = ref << c;
         const uint64_t xref = iref ^ (iref >> 1);
-        for (int w = tid_now(); w < RS; w += bd) lds_ref[w] = has_off ? rows[kp * RS + w] : 0u;
-        for (int w = tid_now(); w < nw * RS; w += bd) lds_seg[w] = 0u;
-        __syncthreads();
-        {
-            const int nb = __builtin_popcountll(xref);
-            for (int e = tid_now(); e < nb * RS; e += bd) {
-                const int j = e / RS, w = e - j * RS;
-                uint64_t m = xref;
-                for (int q = 0; q < j; ++q) m &= m - 1;
-                const int t = __builtin_ctzll(m);
-                if (t < kp) atomicXor(lds_ref + w, rows[t * RS + w]);
-            }
-        }
-        __syncthreads();
-        // lane table b, row v: the rows c - 1 + 3b + j over the set bits j of
-        // v (rows >= kp count as zero), plus Ref in table 0
-        for (int e = tid_now(); e < LANE_ROWS * RS; e += bd) {
-            const int v = e / RS, w = e - v * RS;
-            const int b = v >> 3, vv = v & 7;
-            const int nbits = b < 3 ? 3 : 1;
+        for (int e = tid_now(); e < 4 * RS; e += bd) {
+            const int b = e / RS, w = e - b * RS;
             const int t0 = c - 1 + 3 * b;
-            uint32_t acc = b == 0 ? lds_ref[w] : 0u;
-            for (int t = 0; t < nbits; ++t)
-                if (((vv >> t) & 1) && t0 + t < kp) acc ^= rows[(t0 + t) * RS + w];
-            lds_L[e] = acc;
+            const int nv = b < 3 ? 8 : 2;
+            const uint32_t r0 = t0 < kp ? rows[t0 * RS + w] : 0u;
+            const uint32_t r1 = b < 3 && t0 + 1 < kp ? rows[(t0 + 1) * RS + w] : 0u;
+            const uint32_t r2 = b < 3 && t0 + 2 < kp ? rows[(t0 + 2) * RS + w] : 0u;
+            uint32_t base = 0;
+            if (b == 0) {
+                base = has_off ? rows[kp * RS + w] : 0u;
+                for (int t = c + LANE_BITS - 1; t < kp; ++t)
+                    base ^= rows[t * RS + w] & (0u - (uint32_t)((xref >> t) & 1ull));
+            }
+            uint32_t *dst = lds_L + (8 * b) * RS + w;
+            for (int v = 0; v < nv; ++v)
+                dst[v * RS] = base ^ ((v & 1) ? r0 : 0u) ^ ((v & 2) ? r1 : 0u) ^ ((v & 4) ? r2 : 0u);
         }
+        for (int w = tid_now(); w < nw * RS; w += bd) lds_seg[w] = 0u;
         __syncthreads();
 
         bk.item_cnt = 0;  // results of this item found by this wave
@@ -355,11 +354,23 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                 s2 = st.z;
                 s3 = st.w;
             }
-            uint32_t d[6][4];
+            // The XOR operands of the steps inside a block (rows 0-3, the
+            // phase-1 words): wave-uniform, but held in VGPRs, which issue
+            // faster than scalar operands; they are re-read from LDS after
+            // every check, so that they hold no registers through it.
+            uint32_t d[4][4];
+            auto load_d = [&]() {
 #pragma unroll
-            for (int t = 0; t < 6; ++t)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) d[t][q] = __builtin_amdgcn_readfirstlane(lds_R4[t * 4 + q]);
+                for (int t = 0; t < 4; ++t) {
+                    const uint4 r = *(const uint4 *)(lds_R4 + 4 * t);
+                    d[t][0] = r.x;
+                    d[t][1] = r.y;
+                    d[t][2] = r.z;
+                    d[t][3] = r.w;
+                    asm volatile("" : "+v"(d[t][0]), "+v"(d[t][1]), "+v"(d[t][2]), "+v"(d[t][3]));
+                }
+            };
+            load_d();
 
             const uint64_t nblk = 1ull << (c - 6);
             const int wbase = wv * 64;
@@ -372,70 +383,87 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
             auto uw = [](const uint32_t *q) -> uint32_t { return __builtin_amdgcn_readfirstlane(*opaque(q)); };
             auto iv = [&]() -> wpm_item { return *opaque(items + rfl64((uint64_t)it)); };
             for (uint64_t blk = 0; blk < nblk; ++blk) {
-                // ---- phase 1: fast filter over 64 Gray steps, run as two
-                // interleaved chains: steps 0..31 from the block-start state
-                // and steps 32..63 from the state at step 32 (the low Gray
-                // bits of step 32 are bits 4 and 5).  Steps s and s + 32 flip
-                // the same basis vector, so both chains share the XOR operand;
-                // a step costs 7 VALU ops, and one rarely taken branch covers
-                // two steps and appends the passing lanes to the wave's list
-                // (ballot + mbcnt give the slots).  Steps that would overflow
-                // the list are only marked in a scalar mask and rechecked below.
+                // ---- phase 1: fast filter over 64 Gray steps, run as NC
+                // interleaved chains of 64 / NC steps: chain j starts at step
+                // j * L (L = 64 / NC), whose low Gray bits are those of
+                // jL ^ (jL >> 1).  Steps s + jL flip the same basis vector for
+                // every chain (s + 1 < L), so they share the XOR operand; the
+                // chains' fail words are reduced by 3-input minima and one
+                // compare, and one rarely taken branch appends the passing
+                // lanes of all chains to the wave's list (ballot + mbcnt give
+                // the slots).  Steps that would overflow the list are only
+                // marked in a scalar mask and rechecked below.
+                constexpr int NC = PH1_CHAINS, SL = 64 / NC;
                 uint64_t redo = 0;
-                // rows 4 ^ 5: row 6 of the Gray-bit table of bits 3-5 (read
-                // from LDS: scalar registers are the scarcer resource here)
-                const uint4 r45 = *(const uint4 *)(lds_T + 14 * RS);
-                uint32_t b0 = s0 ^ r45.x, b1 = s1 ^ r45.y, b2 = s2 ^ r45.z, b3 = s3 ^ r45.w;
+                uint32_t c[NC][4];
 #pragma unroll
-                for (int s = 0; s < 32; ++s) {
-                    const uint32_t fa = fail4(s0, s1, s2, s3);
-                    const uint32_t fb = fail4(b0, b1, b2, b3);
-                    const uint32_t fm = fa < fb ? fa : fb;
-                    if (__builtin_expect(__builtin_amdgcn_ballot_w64(fm == 0u) != 0, 0)) {
-                        const uint64_t ba = __builtin_amdgcn_ballot_w64(fa == 0u);
-                        const uint64_t bb = __builtin_amdgcn_ballot_w64(fb == 0u);
-                        const uint32_t na = (uint32_t)__builtin_popcountll(ba);
-                        const uint32_t nb = (uint32_t)__builtin_popcountll(bb);
-                        if (cnt + na + nb <= (uint32_t)LIST_CAP) {
-                            // the lane id, recomputed here (a value kept
-                            // from the kernel start would hold a VGPR)
-                            const uint32_t ln = (uint32_t)lane_now();
-                            const uint32_t e = ((((uint32_t)blk & 63u) << 6 | (uint32_t)s) << 6) | ln;
-                            if (fa == 0u)
-                                lds_W[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(ba >> 32),
-                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)ba, 0u))] = e;
-                            if (fb == 0u)
-                                lds_W[cnt + na + __builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32),
-                                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0u))] =
-                                    e + (32u << 6);
-                            cnt += na + nb;
-                        } else {
-                            redo |= (ba ? 1ull << s : 0ull) | (bb ? 1ull << (s + 32) : 0ull);
-                        }
-                    }
-                    if (s < 31) {
-                        const int t = __builtin_ctz((unsigned)(s + 1));
-                        s0 ^= d[t][0];
-                        s1 ^= d[t][1];
-                        s2 ^= d[t][2];
-                        s3 ^= d[t][3];
-                        b0 ^= d[t][0];
-                        b1 ^= d[t][1];
-                        b2 ^= d[t][2];
-                        b3 ^= d[t][3];
-                        // opaque copies: keep each chain an in-place XOR
-                        // update (re-associating it from the block start
-                        // would hold extra base copies in VGPRs)
-                        asm volatile("" : "+v"(s0), "+v"(s1), "+v"(s2), "+v"(s3));
-                        asm volatile("" : "+v"(b0), "+v"(b1), "+v"(b2), "+v"(b3));
+                for (int j = 0; j < NC; ++j) {
+                    const uint32_t g = (uint32_t)(j * SL) ^ ((uint32_t)(j * SL) >> 1);
+                    if (j == 0) {
+                        c[0][0] = s0; c[0][1] = s1; c[0][2] = s2; c[0][3] = s3;
+                    } else {
+                        const uint4 o0 = *(const uint4 *)(lds_T + (g & 7u) * RS);
+                        const uint4 o1 = *(const uint4 *)(lds_T + (8u + (g >> 3)) * RS);
+                        c[j][0] = xor3(s0, o0.x, o1.x);
+                        c[j][1] = xor3(s1, o0.y, o1.y);
+                        c[j][2] = xor3(s2, o0.z, o1.z);
+                        c[j][3] = xor3(s3, o0.w, o1.w);
                     }
                 }
-                // the second chain ends at step 63: the state the block
+#pragma unroll
+                for (int st = 0; st < SL; ++st) {
+                    uint32_t f[NC];
+#pragma unroll
+                    for (int j = 0; j < NC; ++j) f[j] = fail4(c[j][0], c[j][1], c[j][2], c[j][3]);
+                    uint32_t fm = f[0];
+#pragma unroll
+                    for (int j = 1; j < NC; ++j) fm = fm < f[j] ? fm : f[j];
+                    if (__builtin_expect(__builtin_amdgcn_ballot_w64(fm == 0u) != 0, 0)) {
+                        uint64_t bm[NC];
+                        uint32_t nn[NC], tot = 0;
+#pragma unroll
+                        for (int j = 0; j < NC; ++j) {
+                            bm[j] = __builtin_amdgcn_ballot_w64(f[j] == 0u);
+                            nn[j] = (uint32_t)__builtin_popcountll(bm[j]);
+                            tot += nn[j];
+                        }
+                        if (cnt + tot <= (uint32_t)LIST_CAP) {
+                            const uint32_t ln = (uint32_t)lane_now();
+                            const uint32_t e = ((((uint32_t)blk & 63u) << 6 | (uint32_t)st) << 6) | ln;
+                            uint32_t base = cnt;
+#pragma unroll
+                            for (int j = 0; j < NC; ++j) {
+                                if (f[j] == 0u)
+                                    lds_W[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bm[j] >> 32),
+                                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bm[j], 0u))] =
+                                        e + ((uint32_t)(SL * j) << 6);
+                                base += nn[j];
+                            }
+                            cnt = base;
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < NC; ++j) redo |= bm[j] ? 1ull << (st + SL * j) : 0ull;
+                        }
+                    }
+                    if (st < SL - 1) {
+                        const int t = __builtin_ctz((unsigned)(st + 1));
+#pragma unroll
+                        for (int j = 0; j < NC; ++j) {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) c[j][q] ^= d[t][q];
+                            // opaque copies: keep each chain an in-place XOR
+                            // update (re-associating it from the block start
+                            // would hold extra base copies in VGPRs)
+                            asm volatile("" : "+v"(c[j][0]), "+v"(c[j][1]), "+v"(c[j][2]), "+v"(c[j][3]));
+                        }
+                    }
+                }
+                // the last chain ends at step 63: the state the block
                 // boundary continues from
-                s0 = b0;
-                s1 = b1;
-                s2 = b2;
-                s3 = b3;
+                s0 = c[NC - 1][0];
+                s1 = c[NC - 1][1];
+                s2 = c[NC - 1][2];
+                s3 = c[NC - 1][3];
                 // ---- check the list when it is half full, before the
                 // segment changes and at the end of the item; list the
                 // overflow steps first.  Blocks with nothing to do skip all of
@@ -631,6 +659,7 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                         s2 = sv[2 * bd];
                         s3 = sv[3 * bd];
                     }
+                    load_d();
                 }
                 // ---- block boundary: one more Gray step, flipping t >= 6;
                 // a flip of t >= 12 starts a new segment, whose rows join the

@@ -9,8 +9,9 @@ just its hot loop, must compile without any scratch access: no spill traffic
 reaches memory.  The per-block path -- the basic blocks of the loop holding
 the phase-1 steps that dominate all of its back edges, i.e. run on every
 64-step block -- is checked for its instruction mix: the 64 steps' logic ops,
-no more than 452 VALU instructions, and (at 7 waves) no scalar register
-reloads from VGPR lanes.
+no more than 440 VALU instructions, no scalar register reloads from VGPR
+lanes, and XORs whose two operands are VGPRs (a scalar operand measured
+about 14% slower on the whole sweep).
 """
 import os
 import re
@@ -142,24 +143,8 @@ def test_no_scratch_and_lean_per_block_path(asm, waves, vgprs):
     # the path found is the real one: both chains' two logic ops for 32 steps
     assert sum("bitop3:0x5c" in x for x in path) == 64
     valu = [x for x in path if x.startswith("v_")]
-    assert len(valu) <= 452 + (0 if waves == 7 else 12), len(valu)
-    if waves == 7:
-        assert not [x for x in valu if x.startswith("v_readlane")]
-
-
-@pytest.mark.parametrize("waves,allowed", [(7, 4), (8, 16)])
-def test_phase1_logic_ops_read_three_vgpr_banks(asm, waves, allowed):
-    """The 3-input logic ops of the 64 steps read their three VGPR operands
-    from three different banks (register index mod 4): a shared bank costs
-    issue cycles on every step."""
-    path = per_block_path(asm, f"ILi{waves}E")
-    ops = [x for x in path if x.startswith("v_bitop3_b32") and ("0x5c" in x or "0xe0" in x)]
-    assert len(ops) == 128
-    bad = []
-    for x in ops:
-        regs = re.findall(r"\bv(\d+)\b", x.split("bitop3:")[0])[1:]
-        if len({int(r) % 4 for r in regs}) < 3:
-            bad.append(x)
-    # steps next to the block boundary read chain words from where the
-    # boundary code left them; allow a few
-    assert len(bad) <= allowed, bad
+    assert len(valu) <= 440, len(valu)
+    assert not [x for x in valu if x.startswith("v_readlane")]
+    xors = [x for x in valu if x.startswith("v_xor_b32")]
+    assert len(xors) >= 4 * 60
+    assert not [x for x in xors if re.search(r"\bs\d+\b", x)], "XOR with a scalar operand on the per-block path"
