@@ -482,6 +482,24 @@ int wpm_enumerate(const wpm_batch *batch, const wpm_sched *sched, uint64_t *d_su
                   uint64_t cap, uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats,
                   void *stream);
 
+/*
+ * wpm_enumerate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same sweep and the same outputs, with the dynamic queue's head kept in
+ * a device array of the library instead of sched->d_scratch, which must be
+ * NULL.  The array holds WPM_STATIC_SCRATCH_WORDS uint64 words per device
+ * (the queue needs 2); a schedule needing more is rejected with WPM_ELIMIT.
+ * Each device the library runs on holds its own copy until the process
+ * ends; its address is looked up on the first call on that device.  Every
+ * call on one device shares the array and clears what it uses at its start,
+ * so calls that overlap on one device (streams running concurrently) race:
+ * order them on one stream.  No allocation of any kind is made.
+ */
+#define WPM_STATIC_SCRATCH_WORDS 32
+int wpm_enumerate_noalloc(const wpm_batch *batch, const wpm_sched *sched, uint64_t *d_survivors,
+                          uint64_t cap, uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats,
+                          void *stream);
+
 /* Device facts the scheduler needs: compute units, the s_memrealtime clock
  * rate (kHz, the unit of d_item_times) and the LDS limit per workgroup. */
 int wpm_device_query(int32_t *num_cus, int64_t *wallclock_khz, int32_t *lds_per_block);

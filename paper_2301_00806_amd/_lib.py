@@ -160,6 +160,8 @@ def lib():
     L.wpm_enumerate.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Sched), ctypes.c_void_p,
                                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.c_void_p]
+    L.wpm_enumerate_noalloc.restype = ctypes.c_int
+    L.wpm_enumerate_noalloc.argtypes = L.wpm_enumerate.argtypes
     L.wpm_persistent_grid.restype = ctypes.c_int
     L.wpm_persistent_grid.argtypes = [ctypes.POINTER(Batch), ctypes.c_int32, c_i32p]
     L.wpm_valu_probe.restype = ctypes.c_int
@@ -194,7 +196,7 @@ def check(call: str, status: int, ok=(WPM_OK,)) -> int:
 EXPORTED = ("wpm_strerror", "wpm_last_hip_error", "wpm_build_candidates", "wpm_kernel_basis",
             "wpm_ubt_bound", "wpm_convenient_basis", "wpm_facet_conditions", "wpm_idcm_orbits",
             "wpm_complex_filters", "wpm_iso_classes", "wpm_pack_instance", "wpm_build_queue",
-            "wpm_build_pruned_queue", "wpm_pack_bins", "wpm_enumerate",
+            "wpm_build_pruned_queue", "wpm_pack_bins", "wpm_enumerate", "wpm_enumerate_noalloc",
             "wpm_device_query", "wpm_persistent_grid", "wpm_valu_probe", "wpm_collect", "wpm_mlp_work_floats", "wpm_mlp_forward",
             "wpm_mlp_grad", "wpm_mlp_adam")
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS, MLP_NORM = 16, 64, 2, 5378, 36

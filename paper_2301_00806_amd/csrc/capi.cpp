@@ -4,6 +4,8 @@
 namespace wpm {
 int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t cap,
               uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats, void *stream);
+int enumerate_noalloc(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t cap,
+                      uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats, void *stream);
 int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv, uint64_t cap,
             const uint64_t *d_counts, const uint64_t *d_total, uint64_t *h_counts, uint32_t *h_out,
             int64_t out_cap, int64_t *out_words, int64_t *h_offsets, void *stream);
@@ -111,6 +113,12 @@ int wpm_enumerate(const wpm_batch *batch, const wpm_sched *sched, uint64_t *d_su
                   uint64_t cap, uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats,
                   void *stream) {
     return wpm::enumerate(batch, sched, d_survivors, cap, d_counts, d_total, d_stats, stream);
+}
+
+int wpm_enumerate_noalloc(const wpm_batch *batch, const wpm_sched *sched, uint64_t *d_survivors,
+                          uint64_t cap, uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats,
+                          void *stream) {
+    return wpm::enumerate_noalloc(batch, sched, d_survivors, cap, d_counts, d_total, d_stats, stream);
 }
 
 int wpm_persistent_grid(const wpm_batch *batch, int32_t wg_size, int32_t *grid) {

@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -90,8 +91,11 @@ int persistent_grid_waves(const wpm_batch *b, int wg_size, int waves, int32_t *g
     return WPM_OK;
 }
 
-int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t cap,
-              uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats, void *stream) {
+namespace {
+// The sweep with the dynamic queue's head at d_head (device, >= 2 words).
+int enumerate_with(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t cap,
+                   uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats, uint64_t *d_head,
+                   void *stream) {
     if (!b || !s || !d_counts || !d_total || (cap > 0 && !d_surv)) return WPM_EINVAL;
     if (b->num_instances < 0 || !b->d_tables || !b->d_offsets) return WPM_EINVAL;
     if (b->max_row_words < 4 || b->max_row_words > WPM_MAX_ROW_WORDS || (b->max_row_words & 3))
@@ -102,7 +106,7 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     if (s->mode < WPM_SCHED_PLAIN || s->mode > WPM_SCHED_PACKED) return WPM_EINVAL;
     if (s->mode == WPM_SCHED_PACKED && (!s->d_bin_offsets || s->grid < 1)) return WPM_EINVAL;
     if (s->mode == WPM_SCHED_PLAIN && s->num_items > 0 && !s->h_items) return WPM_EINVAL;
-    if (s->mode == WPM_SCHED_DYNAMIC && !s->d_scratch) return WPM_EINVAL;
+    if (s->mode == WPM_SCHED_DYNAMIC && !d_head) return WPM_EINVAL;
     if (s->waves_per_simd != 0 && s->waves_per_simd != 7 && s->waves_per_simd != 8) return WPM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const int waves = pick_waves(s->waves_per_simd);
@@ -119,13 +123,13 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
         if ((st_rc = zero(d_total, WPM_TOTAL_WORDS, st))) return st_rc;
         if ((st_rc = zero(d_stats, 8, st))) return st_rc;
     }
-    if (s->d_scratch && (st_rc = zero(s->d_scratch, 2, st))) return st_rc;
+    if (d_head && (st_rc = zero(d_head, 2, st))) return st_rc;
     if (s->num_items == 0) return WPM_OK;
 
     KArgs a;
     std::memset(&a, 0, sizeof(a));
     a.num_items = s->num_items;
-    a.head = (unsigned long long *)s->d_scratch;
+    a.head = (unsigned long long *)d_head;
     a.surv = d_surv;
     a.cap = cap;
     a.counts = (unsigned long long *)d_counts;
@@ -166,6 +170,52 @@ int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t
     HIP_TRY(launch_sweep(waves, dim3((unsigned)grid), block, lds, st, b->d_tables, b->d_offsets,
                          s->d_items, a));
     return WPM_OK;
+}
+
+// Scratch of the allocation-free entry point: the dynamic queue's head.
+// Each device holds its own copy of this array (its host-side name is not a
+// device address); its address on a device is looked up once, with that
+// device current, and every call on the device shares it.
+static __device__ __align__(256) unsigned long long scratch[WPM_STATIC_SCRATCH_WORDS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_on_current_device(uint64_t **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return WPM_ELIMIT;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return WPM_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (uint64_t *)g_scratch_ptr[dev];
+    return WPM_OK;
+}
+}  // namespace
+
+int enumerate(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t cap,
+              uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats, void *stream) {
+    if (!s) return WPM_EINVAL;
+    return enumerate_with(b, s, d_surv, cap, d_counts, d_total, d_stats, (uint64_t *)s->d_scratch, stream);
+}
+
+int enumerate_noalloc(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, uint64_t cap,
+                      uint64_t *d_counts, uint64_t *d_total, uint64_t *d_stats, void *stream) {
+    if (!s || s->d_scratch) return WPM_EINVAL;  // the scratch is the library's own
+    // scratch words this schedule needs: the queue head of the dynamic mode
+    const int64_t need = s->mode == WPM_SCHED_DYNAMIC ? 2 : 0;
+    if (need > WPM_STATIC_SCRATCH_WORDS) return WPM_ELIMIT;
+    uint64_t *head = nullptr;
+    if (need) {
+        const int rc = scratch_on_current_device(&head);
+        if (rc) return rc;
+    }
+    return enumerate_with(b, s, d_surv, cap, d_counts, d_total, d_stats, head, stream);
 }
 
 namespace {
