@@ -179,8 +179,11 @@ def main():
                     help="skip the convenient-basis (pruned) sweep of the same batch")
     ap.add_argument("--min-free", type=int, default=0,
                     help="free coordinates a pruned instance keeps (0 = engine default)")
+    ap.add_argument("--records", default="host", choices=["host", "device"],
+                    help="survivor records written by the sweep into pinned host memory (no copy), "
+                         "or into HBM and copied back in parts that overlap the sweep")
     ap.add_argument("--parts", type=int, default=4,
-                    help="sub-launches of the largest class, so that record copies overlap the sweep")
+                    help="device records: sub-launches of the largest class, so that record copies overlap the sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -212,7 +215,7 @@ def main():
         args.cbits = args.cbits or tuned["cbits"]
         args.wg = args.wg or tuned["wg"]
         args.waves = args.waves or tuned.get("waves", 0)
-    sw = E.Sweeper(batch, cap=args.cap)
+    sw = E.Sweeper(batch, cap=args.cap, records_on_host=args.records == "host")
 
     # ---- learned part: labels from timed sweeps of the batch workload, MLP
     # trained on the GPU by the engine's own forward/backward/Adam kernels
@@ -231,8 +234,12 @@ def main():
 
     feats = CM.features_of(preps)
 
-    def plan_learned():
-        cost = S.per_vector_cost(model, feats)       # MLP inference on the GPU
+    # a side stream for the cost model's inference, so that the next step's
+    # plan can be made while the current step's sweep runs
+    side = torch.cuda.Stream()
+
+    def plan_learned(st=None):
+        cost = S.per_vector_cost(model, feats, stream=st)   # MLP inference on the GPU
         return S.make_plan(batch, args.learned_policy, cost=cost, cbits=args.cbits, wg=args.wg,
                            split=not args.no_split)
 
@@ -246,15 +253,25 @@ def main():
         e1 = torch.cuda.Event(enable_timing=True)
         kern_ms, seg_ms, walls = [], {}, []
         t0 = time.perf_counter()
-        for _ in range(steps):
+        # Scheduling is part of every step: the first step's plan is made in
+        # the timed region, and each later one while the step before it
+        # sweeps (host queue building and the model's inference on a side
+        # stream overlap the GPU), as a pipeline over successive batches would.
+        plan = make()
+        for step in range(steps):
             ts = time.perf_counter()
-            plan = make()                              # scheduling is part of the step
             sw.set_items(plan.items, segments=plan.segments)
+            nxt = {}
+
+            def plan_next():
+                if step + 1 < steps:
+                    nxt["plan"] = make(side)
             e0.record(stream)
             # the sweep, with the survivor records copied to pinned host
             # memory while the later sub-launches still run
             rec = sw.launch_fetch(plan.mode, wg_size=args.wg, stream=stream, parts=args.parts,
-                                  seg_events=True, waves=args.waves)
+                                  seg_events=True, waves=args.waves, while_running=plan_next)
+            plan = nxt.get("plan", plan)
             e1 = sw.launch_end
             counts = sw.counts[:n_inst].cpu()          # synchronises the stream
             tot, slots = (int(v) for v in sw.total.cpu()[:2])
@@ -324,15 +341,16 @@ def main():
         f"({cls_vec[dom] / dom_ms * 1e3:.3e} vectors/s); per-class ms {seg_ms}")
     out = {}
     sp = not args.no_split
-    others = [("static", lambda: S.make_plan(batch, "static", cbits=args.cbits, wg=args.wg, split=sp)),
-              ("dynamic_pow2", lambda: S.make_plan(batch, "dynamic", cbits=args.cbits, wg=args.wg, split=sp)),
-              ("packed_pow2", lambda: S.make_plan(batch, "packed", cbits=args.cbits, wg=args.wg, split=sp))]
+    others = [("static", lambda st=None: S.make_plan(batch, "static", cbits=args.cbits, wg=args.wg, split=sp)),
+              ("dynamic_pow2", lambda st=None: S.make_plan(batch, "dynamic", cbits=args.cbits, wg=args.wg, split=sp)),
+              ("packed_pow2", lambda st=None: S.make_plan(batch, "packed", cbits=args.cbits, wg=args.wg, split=sp))]
     if not args.no_plain:
-        others.append(("plain", lambda: S.make_plan(batch, "plain", cbits=args.cbits, wg=args.wg,
+        others.append(("plain", lambda st=None: S.make_plan(batch, "plain", cbits=args.cbits, wg=args.wg,
                                                     plain_min_items=args.plain_min_items, split=sp)))
     other_pol = "packed" if args.learned_policy == "dynamic" else "dynamic"
-    others.append((f"{other_pol}_model", lambda: S.make_plan(
-        batch, other_pol, cost=S.per_vector_cost(model, feats), cbits=args.cbits, wg=args.wg, split=sp)))
+    others.append((f"{other_pol}_model", lambda st=None: S.make_plan(
+        batch, other_pol, cost=S.per_vector_cost(model, feats, stream=st), cbits=args.cbits, wg=args.wg,
+        split=sp)))
     for name, mk in ([] if args.only_learned else others):
         if args.no_static and name == "static":
             continue
@@ -353,11 +371,11 @@ def main():
         visited = batch_p.visited
         log(f"pruned: prepared in {prep_s:.1f}s, visits {visited:.4e} of {vectors:.4e} vectors "
             f"({visited / vectors:.3f})")
-        sw_p = E.Sweeper(batch_p, cap=args.cap)
+        sw_p = E.Sweeper(batch_p, cap=args.cap, records_on_host=args.records == "host")
         feats_p = CM.features_of(preps_p)
 
-        def plan_pruned():
-            cost = S.per_vector_cost(model, feats_p)
+        def plan_pruned(st=None):
+            cost = S.per_vector_cost(model, feats_p, stream=st)
             return S.make_plan(batch_p, "dynamic", cost=cost, cbits=args.cbits, wg=args.wg,
                                split=not args.no_split)
         t_p, k_p, res_p = timed_plan(plan_pruned, args.steps, args.warmup, "pruned-dynamic",
@@ -435,7 +453,8 @@ def main():
         "data": "synthetic (seeded SplitMix64 inputs)",
         "config": {"workload": WORKLOADS[args.workload].format(count=len(preps)),
                    "instances": len(preps), "sum_2k": vectors, "cbits": args.cbits,
-                   "wg_size": args.wg, "waves_per_simd": waves_used, "record_copy_parts": args.parts,
+                   "wg_size": args.wg, "waves_per_simd": waves_used, "records": args.records,
+                   "record_copy_parts": args.parts if args.records == "device" else None,
                    "schedule": f"learned: {args.learned_policy}, LPT on MLP-predicted cost"},
         "wpm_total": int(res_b.total),
         "wpm_counts_sha256": __import__("hashlib").sha256(res_b.counts.tobytes()).hexdigest(),

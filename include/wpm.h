@@ -451,7 +451,9 @@ int wpm_persistent_grid(const wpm_batch *batch, int32_t wg_size, int32_t *grid);
  *   batch       device tables (wpm_pack_instance), see wpm_batch
  *   sched       items (device, and a host copy in PLAIN mode), mode,
  *               workgroup size, grid, register budget
- *   d_survivors [cap][2] uint64 device records {x, instance}.  Waves reserve
+ *   d_survivors [cap][2] uint64 records {x, instance}, in device memory or
+ *               in pinned host memory the device can address (the sweep
+ *               then writes them there directly).  Waves reserve
  *               record slots in chunks, so the slots used may exceed the
  *               results; unused slots hold the sentinel {0, ~0}.  Records are
  *               in no particular order; slots at or beyond cap are not written.

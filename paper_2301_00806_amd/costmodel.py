@@ -70,13 +70,18 @@ class CostModel:
 
     # ------------------------------------------------------------- kernels
     def predict(self, X: np.ndarray, stream=None) -> np.ndarray:
+        """Model outputs for features X, computed on `stream` (default: the
+        current stream); the copies run on that stream too, so a side stream
+        lets the inference overlap work queued on the others."""
         torch = self.torch
-        Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(self.device)
-        Y = torch.empty((len(X), L.MLP_OUT), dtype=torch.float32, device=self.device)
         st = stream or torch.cuda.current_stream()
-        L.check("wpm_mlp_forward", L.lib().wpm_mlp_forward(
-            _vp(self.params), _vp(self.norm), _vp(Xd), len(X), _vp(Y), ctypes.c_void_p(st.cuda_stream)))
-        return Y.cpu().numpy()
+        with torch.cuda.stream(st):
+            Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(self.device)
+            Y = torch.empty((len(X), L.MLP_OUT), dtype=torch.float32, device=self.device)
+            L.check("wpm_mlp_forward", L.lib().wpm_mlp_forward(
+                _vp(self.params), _vp(self.norm), _vp(Xd), len(X), _vp(Y), ctypes.c_void_p(st.cuda_stream)))
+            out = Y.cpu().numpy()
+        return out
 
     def grad(self, Xd, Td, work, gbuf, loss, stream=None):
         torch = self.torch

@@ -274,7 +274,7 @@ int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv,
     }
     std::vector<uint64_t> rec(2 * slots);
     if (slots) {
-        HIP_TRY(hipMemcpyAsync(rec.data(), d_surv, sizeof(uint64_t) * 2 * slots, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(rec.data(), d_surv, sizeof(uint64_t) * 2 * slots, hipMemcpyDefault, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
     uint64_t sum = 0;

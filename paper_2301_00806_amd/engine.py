@@ -486,12 +486,20 @@ class SweepResult:
 class Sweeper:
     """Device buffers and one call of wpm_enumerate over a DeviceBatch."""
 
-    def __init__(self, batch: DeviceBatch, cap: int = 1 << 20, device="cuda"):
+    def __init__(self, batch: DeviceBatch, cap: int = 1 << 20, device="cuda",
+                 records_on_host: bool = False):
+        """With records_on_host, the survivor records live in pinned host
+        memory that the sweep writes directly (no copy back afterwards)."""
         import torch
         self.torch = torch
         self.batch = batch
         self.cap = cap
-        self.surv = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=device)
+        self.records_on_host = records_on_host
+        self.device = torch.device(device)
+        if records_on_host:
+            self.surv = torch.empty((max(cap, 1), 2), dtype=torch.int64, pin_memory=True)
+        else:
+            self.surv = torch.empty((max(cap, 1), 2), dtype=torch.int64, device=device)
         self.counts = torch.empty(max(1, len(batch.preps)), dtype=torch.int64, device=device)
         # [results, record slots, malformed items skipped, 0]
         self.total = torch.empty(L.TOTAL_WORDS, dtype=torch.int64, device=device)
@@ -519,10 +527,10 @@ class Sweeper:
         self._items_host = np.ascontiguousarray(items)
         self._segments = segments
         self._seg_bins = [None if sg.bins is None else torch.from_numpy(
-            np.ascontiguousarray(sg.bins, np.int64)).to(self.surv.device) for sg in segments]
+            np.ascontiguousarray(sg.bins, np.int64)).to(self.device) for sg in segments]
         raw = self._items_host.view(np.int64).reshape(-1) if len(items) else np.zeros(2, np.int64)
-        self._items_dev = torch.from_numpy(raw.copy()).to(self.surv.device)
-        self._times = (torch.zeros((max(1, len(items)), 2), dtype=torch.int64, device=self.surv.device)
+        self._items_dev = torch.from_numpy(raw.copy()).to(self.device)
+        self._times = (torch.zeros((max(1, len(items)), 2), dtype=torch.int64, device=self.device)
                        if want_times else None)
 
     def launch(self, mode: int, wg_size: int = 256, grid: int = 0, stream=None,
@@ -566,7 +574,8 @@ class Sweeper:
                 self.seg_events.append((sg.cls, e0, e1))
 
     def launch_fetch(self, mode: int, wg_size: int = 256, grid: int = 0, stream=None,
-                     parts: int = 4, seg_events: bool = False, waves: int = 0):
+                     parts: int = 4, seg_events: bool = False, waves: int = 0,
+                     while_running=None):
         """Sweep and copy the survivor records to pinned host memory, with the
         copies overlapping the sweep: the largest segment is launched in
         `parts` consecutive item ranges, the record-slot counter is snapshot
@@ -575,11 +584,24 @@ class Sweeper:
         ends), and each finished slot range is copied on a second stream
         while the next launch runs.  Returns a numpy view of all used record
         slots.  With seg_events, self.seg_events holds one (class, start,
-        end) event pair per segment, bracketing all of its launches."""
+        end) event pair per segment, bracketing all of its launches.
+        while_running, if given, is called on the host once every launch is
+        enqueued, before the copies: host work that overlaps the sweep."""
         torch = self.torch
         if stream is None:
             stream = torch.cuda.current_stream()
         segs = list(self._segments or [Segment(None, 0, 0)])
+        if self.records_on_host:
+            # the sweep writes the records into host memory itself: one
+            # launch per segment, nothing to copy afterwards
+            self.launch(mode, wg_size=wg_size, grid=grid, stream=stream, seg_events=seg_events,
+                        waves=waves)
+            self.launch_end = torch.cuda.Event(enable_timing=True)
+            self.launch_end.record(stream)
+            if while_running is not None:
+                while_running()
+            stream.synchronize()
+            return self.surv[:min(int(self.total[1].item()), self.cap)].numpy()
         if mode == L.SCHED_PACKED:
             parts = 1
         big = max(range(len(segs)), key=lambda i: segs[i].end - segs[i].start)
@@ -590,10 +612,10 @@ class Sweeper:
             cuts = [sg.start + (n * j) // k for j in range(k + 1)]
             runs += [(i, cuts[j], cuts[j + 1]) for j in range(k)]
         if getattr(self, "_snap", None) is None or self._snap.numel() < len(runs):
-            self._snap = torch.zeros(max(8, len(runs)), dtype=torch.int64, device=self.surv.device)
+            self._snap = torch.zeros(max(8, len(runs)), dtype=torch.int64, device=self.device)
             self._snap_host = torch.zeros(max(8, len(runs)), dtype=torch.int64, pin_memory=True)
         if getattr(self, "_copy_stream", None) is None:
-            self._copy_stream = torch.cuda.Stream(device=self.surv.device)
+            self._copy_stream = torch.cuda.Stream(device=self.device)
         if getattr(self, "_pinned", None) is None or self._pinned.shape[0] < self.cap:
             self._pinned = torch.empty((max(self.cap, 1), 2), dtype=torch.int64, pin_memory=True)
         items = self._items_host
@@ -633,6 +655,8 @@ class Sweeper:
         # end of the sweep on `stream` (before the host waits for copies)
         self.launch_end = torch.cuda.Event(enable_timing=True)
         self.launch_end.record(stream)
+        if while_running is not None:
+            while_running()
         cs = self._copy_stream
         prev = 0
         for r, ev in enumerate(ends):
@@ -651,11 +675,15 @@ class Sweeper:
     def fetch_records(self, n: Optional[int] = None):
         """Copy the first n record slots (default: all used slots) into a
         pinned host buffer (allocated once) and return a numpy view of them.
-        Unused slots carry the instance ~0 and are kept in the view."""
+        Unused slots carry the instance ~0 and are kept in the view.  Records
+        that already live in host memory are returned as a view, uncopied."""
         torch = self.torch
         if n is None:
             n = int(self.total[1].item())
         n = min(int(n), self.cap)
+        if self.records_on_host:
+            torch.cuda.current_stream().synchronize()
+            return self.surv[:n].numpy()
         if getattr(self, "_pinned", None) is None or self._pinned.shape[0] < n:
             self._pinned = torch.empty((max(n, 1), 2), dtype=torch.int64, pin_memory=True)
         if n:

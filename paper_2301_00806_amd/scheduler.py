@@ -35,9 +35,9 @@ class Plan:
     predicted_makespan: float = 0.0
 
 
-def per_vector_cost(model, features: np.ndarray) -> np.ndarray:
+def per_vector_cost(model, features: np.ndarray, stream=None) -> np.ndarray:
     """ns per vector from the model (its first output is ln ns/vector)."""
-    y = model.predict(features)
+    y = model.predict(features, stream=stream)
     return np.exp(np.clip(y[:, 0], -20.0, 20.0)).astype(np.float32)
 
 

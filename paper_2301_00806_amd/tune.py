@@ -1,8 +1,10 @@
 """Autotuner for the persistent sweep: lane chunk bits, workgroup size and
 the kernel's register budget (7 or 8 waves per SIMD).
 
-It times candidate launch shapes on a sample of the batch (the instances that
-hold most of the work, plus a spread of small ones), keeps the fastest, and
+It times candidate launch shapes on the batch itself when a sweep of it takes
+well under a second, else on a sample that keeps the batch's mix (every
+instance whose index falls on a stride, so that large and small kernels are
+represented as in the batch), keeps the fastest, and
 caches the choice in a JSON file keyed by the GPU architecture, the kernel
 source and a shape bucket of the batch (widest table row, log2 of the vectors
 per instance, pruned or not).  Counts are identical for every shape; the
@@ -21,8 +23,8 @@ from . import _lib as L
 from . import engine as E
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "wpm_tune.json")
-CBITS = (10, 11, 12, 13, 14, 16)
-WGS = (128, 256)
+CBITS = (10, 11, 12, 13, 14)
+WGS = (256,)
 WAVES = (7, 8)
 
 
@@ -40,22 +42,21 @@ def shape_key(batch: "E.DeviceBatch") -> str:
 
 
 def _sample(preps, budget_vectors: float):
-    order = sorted(range(len(preps)), key=lambda i: -preps[i].visited)
-    chosen, tot = [], 0.0
-    for i in order:
-        v = float(preps[i].visited)
-        if tot + v > budget_vectors and chosen:
-            continue
-        chosen.append(i)
-        tot += v
-        if tot >= budget_vectors:
-            break
-    small = [i for i in order[::max(1, len(order) // 64)] if i not in chosen]
-    return sorted(set(chosen + small))
+    """All instances when their vectors fit the budget, else every s-th
+    instance with the smallest stride s that fits it."""
+    total = float(sum(p.visited for p in preps))
+    if total <= budget_vectors:
+        return list(range(len(preps)))
+    stride = int(np.ceil(total / budget_vectors))
+    while True:
+        idx = list(range(0, len(preps), stride))
+        if float(sum(preps[i].visited for i in idx)) <= budget_vectors or stride > len(preps):
+            return idx
+        stride += 1
 
 
-def tune(preps: Sequence, cache: Optional[str] = DEFAULT_CACHE, budget_vectors: float = 2e11,
-         cbits=CBITS, wgs=WGS, waves=WAVES, repeats: int = 2, force: bool = False, log=None) -> Dict:
+def tune(preps: Sequence, cache: Optional[str] = DEFAULT_CACHE, budget_vectors: float = 3e12,
+         cbits=CBITS, wgs=WGS, waves=WAVES, repeats: int = 1, force: bool = False, log=None) -> Dict:
     import torch
     full = E.DeviceBatch(preps)
     key = shape_key(full)
@@ -71,7 +72,7 @@ def tune(preps: Sequence, cache: Optional[str] = DEFAULT_CACHE, budget_vectors: 
     idx = _sample(preps, budget_vectors)
     sub = [preps[i] for i in idx]
     batch = E.DeviceBatch(sub)
-    sw = E.Sweeper(batch, cap=1 << 24)
+    sw = E.Sweeper(batch, cap=1 << 26)
     vec = batch.visited
     results, ref = [], None
     for wg in wgs:

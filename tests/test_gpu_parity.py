@@ -143,6 +143,27 @@ def test_overlapped_record_copies_match_plain_launch(E):
         assert len(got) == int(want_counts.sum())
 
 
+def test_records_in_pinned_host_memory(E):
+    # the sweep writes its records straight into pinned host memory: the same
+    # counts and the same records as with records in device memory
+    insts = [i for i in W.batch(E.kdim, count=96) if i.meta["k"] <= 24][:32]
+    preps = E.prepare_many(insts)
+    batch = E.DeviceBatch(preps)
+    items = E.build_queue(batch.k, 10, 256)
+    out = []
+    for host in (False, True):
+        sw = E.Sweeper(batch, cap=1 << 22, records_on_host=host)
+        sw.set_items(items)
+        _say(f"[gpu] records on host: {host}")
+        rec = sw.launch_fetch(2, wg_size=256).copy()
+        rec = rec[rec[:, 1] != -1]
+        out.append((sw.counts[:len(preps)].cpu().numpy(), rec[np.lexsort((rec[:, 0], rec[:, 1]))]))
+        if host:
+            assert sw.collect() == oracle_sets(preps)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert len(out[1][1]) == int(out[1][0].sum())
+
+
 def test_capacity_overflow_keeps_counts_exact(E):
     from paper_2301_00806_amd import _lib as L
     f = W.fano()
