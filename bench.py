@@ -395,10 +395,17 @@ def main():
     ok = np.isfinite(Tte[:, 0])
     err = pred[ok, 0] - Tte[ok, 0]
     base = np.median(Ttr[okt, 0]) - Tte[ok, 0]     # "cost proportional to 2^k": constant ns/vector
+    # the large instances: those holding 90% of the vectors
+    vec_ok = np.array([float(1 << p.k) for p in preps])[ok]
+    big = np.argsort(-vec_ok)
+    big = big[:int(np.searchsorted(np.cumsum(vec_ok[big]) / vec_ok.sum(), 0.9)) + 1]
     model_err = {"log_rmse": float(np.sqrt(np.mean(err ** 2))),
                  "mape": float(np.mean(np.abs(np.expm1(err)))),
                  "log_rmse_pow2_heuristic": float(np.sqrt(np.mean(base ** 2))),
                  "mape_pow2_heuristic": float(np.mean(np.abs(np.expm1(base)))),
+                 "large_instances": int(len(big)),
+                 "log_rmse_large": float(np.sqrt(np.mean(err[big] ** 2))),
+                 "log_rmse_pow2_heuristic_large": float(np.sqrt(np.mean(base[big] ** 2))),
                  "train_instances": len(Xtr), "train_loss": train_loss}
     log(f"model error on fresh instances: {model_err}")
 

@@ -220,17 +220,18 @@ int enumerate_noalloc(const wpm_batch *b, const wpm_sched *s, uint64_t *d_surv, 
 
 namespace {
 
-// Run fn(i) for i in [0, num) on up to 16 host threads (dynamic chunks).
+// Run fn(i) for i in [0, num) on up to 16 host threads (dynamic chunks of
+// `grain`).
 template <class Fn>
-void host_parallel_for(int64_t num, Fn fn) {
+void host_parallel_for(int64_t num, Fn fn, int64_t grain = 16) {
     const int hw = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    const int nt = (int)std::min<int64_t>(hw, std::max<int64_t>(1, num));
+    const int nt = (int)std::min<int64_t>(hw, std::max<int64_t>(1, (num + grain - 1) / grain));
     std::atomic<int64_t> next{0};
     auto work = [&]() {
         for (;;) {
-            const int64_t a = next.fetch_add(16);
+            const int64_t a = next.fetch_add(grain);
             if (a >= num) break;
-            for (int64_t i = a; i < std::min(num, a + 16); ++i) fn(i);
+            for (int64_t i = a; i < std::min(num, a + grain); ++i) fn(i);
         }
     };
     std::vector<std::thread> th;
@@ -239,18 +240,70 @@ void host_parallel_for(int64_t num, Fn fn) {
     for (auto &t : th) t.join();
 }
 
-// K = offset + sum of the basis vectors selected by x, as W words.
-inline void expand_x(const wpm_host_instance &in, uint64_t x, uint32_t *K) {
-    const int W = (in.M + 31) / 32;
-    for (int w = 0; w < W; ++w) K[w] = in.offset ? in.offset[w] : 0u;
-    for (uint64_t b = x; b; b &= b - 1) {
-        const int t = __builtin_ctzll(b);
-        for (int w = 0; w < W; ++w) K[w] ^= in.basis[(size_t)t * W + w];
+// One instance's facets in increasing vertex-mask order, and its basis (and
+// coset offset) with the facet bits moved to those positions: the set bits of
+// a complex's bit vector, read in increasing position, are then its facets in
+// increasing mask order.
+struct SortedFacets {
+    int W = 0;
+    std::vector<uint32_t> mask;   // [M] facet masks, increasing
+    std::vector<uint32_t> basis;  // [k][W] permuted basis rows
+    std::vector<uint32_t> off;    // [W] permuted offset (zero for a subspace)
+};
+
+SortedFacets sort_facets(const wpm_host_instance &in) {
+    SortedFacets sf;
+    const int M = in.M, W = (M + 31) / 32;
+    sf.W = W;
+    std::vector<int32_t> order(M);
+    for (int j = 0; j < M; ++j) order[j] = j;
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return in.facets[a] < in.facets[b]; });
+    std::vector<int32_t> pos(M);
+    sf.mask.resize(M);
+    for (int r = 0; r < M; ++r) {
+        pos[order[r]] = r;
+        sf.mask[r] = in.facets[order[r]];
     }
+    auto permute = [&](const uint32_t *src, uint32_t *dst) {
+        for (int w = 0; w < W; ++w)
+            for (uint32_t v = src[w]; v; v &= v - 1) {
+                const int r = pos[w * 32 + __builtin_ctz(v)];
+                dst[r >> 5] |= 1u << (r & 31);
+            }
+    };
+    sf.basis.assign((size_t)in.k * W, 0u);
+    for (int t = 0; t < in.k; ++t) permute(in.basis + (size_t)t * W, sf.basis.data() + (size_t)t * W);
+    sf.off.assign((size_t)W, 0u);
+    if (in.offset) permute(in.offset, sf.off.data());
+    return sf;
+}
+
+// Canonical order of two complexes given as permuted bit vectors (facets in
+// increasing mask order): lexicographic order of their facet lists, a list
+// that is a prefix of another coming first.  At the lowest differing position
+// j the complex holding j continues with facet j; the other continues with a
+// later facet (j comes first) or has ended (it comes first).
+inline bool canon_less(const uint32_t *A, const uint32_t *B, int W) {
+    for (int w = 0; w < W; ++w) {
+        const uint32_t d = A[w] ^ B[w];
+        if (!d) continue;
+        const int b = __builtin_ctz(d);
+        const bool a_has = (A[w] >> b) & 1u;
+        const uint32_t *other = a_has ? B : A;
+        const uint32_t above = b == 31 ? 0u : (other[w] >> (b + 1));
+        bool more = above != 0u;
+        for (int v = w + 1; v < W && !more; ++v) more = other[v] != 0u;
+        return a_has == more;
+    }
+    return false;
 }
 
 }  // namespace
 
+// Host expansion of the records into canonical facet lists.  The records are
+// grouped by instance with a counting sort (host threads over slot ranges);
+// each instance then expands its x values into permuted bit vectors, sorts
+// them canonically, and writes [len, facets...] per complex.
 int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv, uint64_t cap,
             const uint64_t *d_counts, const uint64_t *d_total, uint64_t *h_counts, uint32_t *h_out,
             int64_t out_cap, int64_t *out_words, int64_t *h_offsets, void *stream) {
@@ -272,45 +325,75 @@ int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv,
         *out_words = -(int64_t)slots;  // record slots needed
         return WPM_ECAP;
     }
-    std::vector<uint64_t> rec(2 * slots);
-    if (slots) {
-        HIP_TRY(hipMemcpyAsync(rec.data(), d_surv, sizeof(uint64_t) * 2 * slots, hipMemcpyDefault, st));
-        HIP_TRY(hipStreamSynchronize(st));
-    }
     uint64_t sum = 0;
     for (int i = 0; i < num; ++i) sum += h_counts[i];
     if (sum != total) return WPM_EINVAL;  // counts and total disagree: corrupted buffers
-    // group the records by instance (counting sort; unused slots carry ~0)
-    std::vector<int64_t> start((size_t)num + 1, 0);
-    uint64_t found = 0;
-    for (uint64_t r = 0; r < slots; ++r) {
-        const uint64_t inst = rec[2 * r + 1];
-        if (inst == ~0ull) continue;
-        if (inst >= (uint64_t)num) return WPM_EINVAL;
-        const uint64_t x = rec[2 * r];
-        if (insts[inst].k < 64 && (x >> insts[inst].k)) return WPM_EINVAL;
-        ++start[inst + 1];
-        ++found;
-    }
-    if (found != total) return WPM_EINVAL;
-    for (int i = 0; i < num; ++i) {
-        if ((uint64_t)start[i + 1] != h_counts[i]) return WPM_EINVAL;
-        start[i + 1] += start[i];
-    }
-    std::vector<uint64_t> xs((size_t)found);
+    // the records: read in place when they are in host memory, else copied
+    const uint64_t *rec = d_surv;
+    std::vector<uint64_t> rec_copy;
     {
-        std::vector<int64_t> fill(start.begin(), start.end() - 1);
-        for (uint64_t r = 0; r < slots; ++r)
-            if (rec[2 * r + 1] != ~0ull) xs[(size_t)fill[rec[2 * r + 1]]++] = rec[2 * r];
+        hipPointerAttribute_t attr;
+        const bool host = hipPointerGetAttributes(&attr, d_surv) == hipSuccess &&
+                          attr.type == hipMemoryTypeHost;
+        (void)hipGetLastError();
+        if (!host && slots) {
+            rec_copy.resize(2 * slots);
+            HIP_TRY(hipMemcpyAsync(rec_copy.data(), d_surv, sizeof(uint64_t) * 2 * slots, hipMemcpyDefault, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            rec = rec_copy.data();
+        }
     }
+    // group the records by instance: per-range histograms, then scatter
+    const int64_t ranges = std::max<int64_t>(1, std::min<int64_t>(64, (int64_t)(slots / 65536) + 1));
+    const uint64_t per = (slots + ranges - 1) / (uint64_t)ranges;
+    std::vector<int64_t> hist((size_t)ranges * (size_t)num, 0);
+    std::atomic<int> bad{0};
+    host_parallel_for(ranges, [&](int64_t r) {
+        int64_t *h = hist.data() + (size_t)r * num;
+        const uint64_t e = std::min<uint64_t>(slots, (uint64_t)(r + 1) * per);
+        for (uint64_t q = (uint64_t)r * per; q < e; ++q) {
+            const uint64_t inst = rec[2 * q + 1];
+            if (inst == ~0ull) continue;
+            if (inst >= (uint64_t)num) { bad = 1; return; }
+            const uint64_t x = rec[2 * q];
+            if (insts[inst].k < 64 && (x >> insts[inst].k)) { bad = 1; return; }
+            ++h[inst];
+        }
+    }, 1);
+    if (bad) return WPM_EINVAL;
+    std::vector<int64_t> start((size_t)num + 1, 0);
+    for (int i = 0; i < num; ++i) {
+        int64_t c = 0;
+        for (int64_t r = 0; r < ranges; ++r) {
+            int64_t &h = hist[(size_t)r * num + i];
+            const int64_t v = h;
+            h = start[i] + c;  // this range's first position for instance i
+            c += v;
+        }
+        if ((uint64_t)c != h_counts[i]) return WPM_EINVAL;
+        start[i + 1] = start[i] + c;
+    }
+    std::vector<uint64_t> xs((size_t)start[num]);
+    host_parallel_for(ranges, [&](int64_t r) {
+        int64_t *h = hist.data() + (size_t)r * num;
+        const uint64_t e = std::min<uint64_t>(slots, (uint64_t)(r + 1) * per);
+        for (uint64_t q = (uint64_t)r * per; q < e; ++q) {
+            const uint64_t inst = rec[2 * q + 1];
+            if (inst != ~0ull) xs[(size_t)h[inst]++] = rec[2 * q];
+        }
+    }, 1);
     // words per instance: one length word plus |K| facets per complex
     std::vector<int64_t> iw((size_t)num, 0);
     host_parallel_for(num, [&](int64_t i) {
-        uint32_t K[WPM_MAX_M / 32];
         const int W = (insts[i].M + 31) / 32;
         int64_t w = 0;
+        uint32_t K[WPM_MAX_M / 32];
         for (int64_t r = start[i]; r < start[i + 1]; ++r) {
-            expand_x(insts[i], xs[(size_t)r], K);
+            for (int q = 0; q < W; ++q) K[q] = insts[i].offset ? insts[i].offset[q] : 0u;
+            for (uint64_t b = xs[(size_t)r]; b; b &= b - 1) {
+                const uint32_t *row = insts[i].basis + (size_t)__builtin_ctzll(b) * W;
+                for (int q = 0; q < W; ++q) K[q] ^= row[q];
+            }
             w += 1;
             for (int q = 0; q < W; ++q) w += __builtin_popcount(K[q]);
         }
@@ -324,36 +407,39 @@ int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv,
     h_offsets[num] = words;
     *out_words = words;
     if (!h_out || out_cap < words) return WPM_ECAP;
-    // expand each complex to its sorted facet list; order the complexes of an
-    // instance lexicographically (the canonical form)
+    // per instance: permuted bit vectors, canonical sort, facet lists
     host_parallel_for(num, [&](int64_t i) {
         const int64_t n_i = start[i + 1] - start[i];
         if (!n_i) return;
-        const int W = (insts[i].M + 31) / 32;
-        std::vector<uint32_t> flat;
-        std::vector<int64_t> beg((size_t)n_i + 1, 0);
-        flat.reserve((size_t)(iw[(size_t)i] - n_i));
-        uint32_t K[WPM_MAX_M / 32];
+        const SortedFacets sf = sort_facets(insts[i]);
+        const int W = sf.W;
+        std::vector<uint32_t> kv((size_t)n_i * (size_t)std::max(W, 1));
         for (int64_t r = 0; r < n_i; ++r) {
-            expand_x(insts[i], xs[(size_t)(start[i] + r)], K);
-            const size_t b0 = flat.size();
-            for (int w = 0; w < W; ++w)
-                for (uint32_t v = K[w]; v; v &= v - 1) flat.push_back(insts[i].facets[w * 32 + __builtin_ctz(v)]);
-            std::sort(flat.begin() + (long)b0, flat.end());
-            beg[(size_t)r + 1] = (int64_t)flat.size();
+            uint32_t *K = kv.data() + (size_t)r * W;
+            for (int q = 0; q < W; ++q) K[q] = sf.off[q];
+            for (uint64_t b = xs[(size_t)(start[i] + r)]; b; b &= b - 1) {
+                const uint32_t *row = sf.basis.data() + (size_t)__builtin_ctzll(b) * W;
+                for (int q = 0; q < W; ++q) K[q] ^= row[q];
+            }
         }
         std::vector<int64_t> idx((size_t)n_i);
         for (int64_t r = 0; r < n_i; ++r) idx[(size_t)r] = r;
         std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
-            return std::lexicographical_compare(flat.begin() + beg[a], flat.begin() + beg[a + 1],
-                                                flat.begin() + beg[b], flat.begin() + beg[b + 1]);
+            return canon_less(kv.data() + (size_t)a * W, kv.data() + (size_t)b * W, W);
         });
         int64_t w = h_offsets[i];
         for (int64_t r : idx) {
-            h_out[w++] = (uint32_t)(beg[r + 1] - beg[r]);
-            for (int64_t q = beg[r]; q < beg[r + 1]; ++q) h_out[w++] = flat[(size_t)q];
+            const uint32_t *K = kv.data() + (size_t)r * W;
+            uint32_t *len = h_out + w++;
+            uint32_t n = 0;
+            for (int q = 0; q < W; ++q)
+                for (uint32_t v = K[q]; v; v &= v - 1) {
+                    h_out[w++] = sf.mask[q * 32 + __builtin_ctz(v)];
+                    ++n;
+                }
+            *len = n;
         }
-    });
+    }, 1);
     return WPM_OK;
 }
 

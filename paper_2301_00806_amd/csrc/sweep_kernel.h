@@ -617,32 +617,34 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                                     if (bal) {
                                         const uint32_t nbal = (uint32_t)__builtin_popcountll(bal);
                                         bk.item_cnt += nbal;
-                                        uint64_t out_pos = bk.out_pos, out_end = bk.out_end;
-                                        if (out_pos + nbal > out_end) {
-                                            // close the current chunk with sentinel
-                                            // records and reserve a new one (one
-                                            // global atomic per a.chunk record slots)
-                                            for (uint64_t e0 = out_pos + (uint64_t)lane_now(); e0 < out_end && e0 < a.cap;
-                                                 e0 += 64) {
-                                                a.surv[2 * e0] = 0;
-                                                a.surv[2 * e0 + 1] = ~0ull;
-                                            }
-                                            const uint64_t want = a.chunk > nbal ? a.chunk : nbal;
+                                        // the wave's current chunk of record slots
+                                        // is [out_pos, out_end); results that do
+                                        // not fit continue at the start of a newly
+                                        // reserved chunk (one global atomic per
+                                        // a.chunk slots), so slots stay unused only
+                                        // at the end of each wave's last chunk
+                                        const uint64_t out_pos = bk.out_pos;
+                                        uint64_t out_end = bk.out_end;
+                                        const uint32_t room = (uint32_t)(out_end - out_pos);
+                                        uint64_t next = 0;
+                                        if (nbal > room) {
+                                            const uint64_t over = nbal - room;
+                                            const uint64_t want = a.chunk > over ? a.chunk : over;
                                             unsigned long long rbase = 0;
                                             if (lane_now() == 0) rbase = atomicAdd(a.total + TOT_SLOTS, (unsigned long long)want);
-                                            out_pos = rfl64(rbase);
-                                            out_end = out_pos + want;
+                                            next = rfl64(rbase);
+                                            out_end = next + want;
                                         }
                                         if (ok) {
                                             const uint32_t rk = __builtin_amdgcn_mbcnt_hi(
                                                 (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                                            const uint64_t pos = out_pos + rk;
+                                            const uint64_t pos = rk < room ? out_pos + rk : next + (rk - room);
                                             if (pos < a.cap) {
                                                 a.surv[2 * pos] = x;
                                                 a.surv[2 * pos + 1] = __builtin_amdgcn_readfirstlane(ci.instance);
                                             }
                                         }
-                                        bk.out_pos = out_pos + nbal;
+                                        bk.out_pos = nbal > room ? next + (nbal - room) : out_pos + nbal;
                                         bk.out_end = out_end;
                                     }
                                 }
