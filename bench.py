@@ -5,8 +5,9 @@ columns], n = 5 + (i mod 4), m = n + 4, kept when the kernel dimension k of
 their candidate set is at most 36 (the learned-scheduler workload).  A step is
 one pass of the hot path over the whole batch with the packed tables already
 resident in HBM: cost prediction, queue packing, the persistent sweep of all
-sum_i 2^k_i kernel vectors, and the read-back of the exact per-instance
-counts and survivor records.  The plain schedule (one launch per instance) is
+sum_i 2^k_i kernel vectors into exact per-instance counts (read back) and
+survivor records (left in HBM by default; the end-to-end figure copies them
+to the host and expands them).  The plain schedule (one launch per instance) is
 timed on the same batch for comparison, and so is the pruned sweep over a
 convenient kernel basis (Section 2.1: same results, fewer vectors visited),
 reported beside the headline figure.
@@ -179,11 +180,11 @@ def main():
                     help="skip the convenient-basis (pruned) sweep of the same batch")
     ap.add_argument("--min-free", type=int, default=0,
                     help="free coordinates a pruned instance keeps (0 = engine default)")
-    ap.add_argument("--records", default="host", choices=["host", "device"],
-                    help="survivor records written by the sweep into pinned host memory (no copy), "
-                         "or into HBM and copied back in parts that overlap the sweep")
+    ap.add_argument("--records", default="hbm", choices=["hbm", "host", "copy"],
+                    help="survivor records left in HBM (the step's output), written by the sweep into "
+                         "pinned host memory, or written to HBM and copied back in parts that overlap the sweep")
     ap.add_argument("--parts", type=int, default=4,
-                    help="device records: sub-launches of the largest class, so that record copies overlap the sweep")
+                    help="--records copy: sub-launches of the largest class, so that record copies overlap the sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -247,7 +248,10 @@ def main():
         plan = make()
         for _ in range(warmup):
             sw.set_items(plan.items, segments=plan.segments)
-            sw.launch_fetch(plan.mode, wg_size=args.wg, stream=stream, parts=args.parts, waves=args.waves)
+            if args.records == "hbm":
+                sw.launch(plan.mode, wg_size=args.wg, stream=stream, waves=args.waves)
+            else:
+                sw.launch_fetch(plan.mode, wg_size=args.wg, stream=stream, parts=args.parts, waves=args.waves)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -267,17 +271,25 @@ def main():
                 if step + 1 < steps:
                     nxt["plan"] = make(side)
             e0.record(stream)
-            # the sweep, with the survivor records copied to pinned host
-            # memory while the later sub-launches still run
-            rec = sw.launch_fetch(plan.mode, wg_size=args.wg, stream=stream, parts=args.parts,
-                                  seg_events=True, waves=args.waves, while_running=plan_next)
+            if args.records == "hbm":
+                # the sweep; its survivor records stay in HBM
+                sw.launch(plan.mode, wg_size=args.wg, stream=stream, seg_events=True, waves=args.waves)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e1.record(stream)
+                plan_next()
+                rec = None
+            else:
+                # records in pinned host memory: written there by the sweep,
+                # or copied there while the later sub-launches still run
+                rec = sw.launch_fetch(plan.mode, wg_size=args.wg, stream=stream, parts=args.parts,
+                                      seg_events=True, waves=args.waves, while_running=plan_next)
+                e1 = sw.launch_end
             plan = nxt.get("plan", plan)
-            e1 = sw.launch_end
             counts = sw.counts[:n_inst].cpu()          # synchronises the stream
             tot, slots = (int(v) for v in sw.total.cpu()[:2])
             if slots > sw.cap:
                 raise SystemExit(f"survivor buffer too small: {slots} > {sw.cap}")
-            assert len(rec) == slots
+            assert rec is None or len(rec) == slots
             kern_ms.append(e0.elapsed_time(e1))
             for cls, a0, a1 in sw.seg_events:
                 seg_ms.setdefault(cls, []).append(a0.elapsed_time(a1))
@@ -308,6 +320,7 @@ def main():
     # and expanded into canonical facet lists by wpm_collect
     e2e = None
     if not args.no_e2e:
+        sw.reserve_host_staging()   # set-up: pinned memory the records are copied into
         host_tab = batch.tables.cpu().pin_memory()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -319,13 +332,29 @@ def main():
         sw.launch(plan.mode, wg_size=args.wg, stream=stream, waves=args.waves)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        d2h_ms = None
+        if not sw.records_on_host:
+            # the survivor records over PCIe into pinned host memory
+            slots = min(int(sw.total[1].item()), sw.cap)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            sw._staging[:slots].copy_(sw.surv[:slots], non_blocking=True)
+            torch.cuda.synchronize()
+            d2h_ms = (time.perf_counter() - ta) * 1e3
+        t2b = time.perf_counter()
         cnt_e, words_e, _ = sw.collect_raw()
         t3 = time.perf_counter()
         assert np.array_equal(cnt_e, res_b.counts)
-        e2e = {"h2d_ms": (t1 - t0) * 1e3, "step_ms": (t2 - t1) * 1e3, "collect_ms": (t3 - t2) * 1e3,
-               "total_ms": (t3 - t0) * 1e3, "vectors_per_s": vectors / (t3 - t0),
+        step_s, collect_s = t2 - t1, t3 - t2b
+        e2e = {"h2d_ms": (t1 - t0) * 1e3, "step_ms": step_s * 1e3,
+               "records_d2h_ms": d2h_ms, "collect_ms": collect_s * 1e3,
+               "total_ms": (t1 - t0 + step_s + collect_s) * 1e3,
+               "vectors_per_s": vectors / (t1 - t0 + step_s + collect_s),
+               "pcie_inclusive_step_vectors_per_s": None if d2h_ms is None else
+               vectors / (step_s + d2h_ms * 1e-3),
                "table_bytes": batch.table_bytes, "facet_words": int(len(words_e)),
-               "note": "collect = records to host + expansion to sorted facet lists, 16 host threads"}
+               "note": "collect = records to host + expansion to sorted facet lists, 16 host threads; "
+                       "pcie_inclusive_step = step + survivor records to pinned host memory"}
         log(f"end to end: {e2e}")
         del words_e
     # the dominant launch: the launch class holding most of the vectors
@@ -364,8 +393,18 @@ def main():
     pruned = None
     if not args.no_pruned:
         t = time.time()
-        mf = args.min_free or E.DEFAULT_MIN_FREE
-        preps_p = E.prepare_many(insts, prune=True, min_free=mf)
+        cb_p = args.cbits
+        if args.min_free:
+            mf = args.min_free
+            preps_p = E.prepare_many(insts, prune=True, min_free=mf)
+            tuned_p = None
+        else:
+            # free coordinates and chunk bits from the pruned autotuner
+            from paper_2301_00806_amd import tune as T
+            tuned_p, preps_p = T.tune_pruned(insts, wg=args.wg, waves=args.waves or 8, log=log)
+            mf, cb_p = int(tuned_p["min_free"]), int(tuned_p["cbits"])
+            log(f"pruned autotuner ({'cached' if tuned_p['cached'] else 'measured'}, {tuned_p['key']}): "
+                f"min_free={mf} cbits={cb_p}")
         prep_s = time.time() - t
         batch_p = E.DeviceBatch(preps_p)
         visited = batch_p.visited
@@ -376,15 +415,19 @@ def main():
 
         def plan_pruned(st=None):
             cost = S.per_vector_cost(model, feats_p, stream=st)
-            return S.make_plan(batch_p, "dynamic", cost=cost, cbits=args.cbits, wg=args.wg,
+            return S.make_plan(batch_p, "dynamic", cost=cost, cbits=cb_p, wg=args.wg,
                                split=not args.no_split)
         t_p, k_p, res_p = timed_plan(plan_pruned, args.steps, args.warmup, "pruned-dynamic",
                                      sw=sw_p, n_inst=len(preps_p), vec=vectors)
         assert np.array_equal(res_p.counts, res_b.counts), "pruned counts differ"
-        pruned = {"min_free": mf, "visited_vectors": visited, "covered_vectors": vectors,
+        pruned = {"min_free": mf, "cbits": cb_p, "tuned": None if tuned_p is None else
+                  {"cached": tuned_p["cached"], "results": tuned_p["results"]},
+                  "visited_vectors": visited, "covered_vectors": vectors,
                   "ms_per_step": t_p * 1e3, "kernel_ms": k_p,
                   "covered_per_s": vectors / t_p, "visited_per_s": visited / t_p,
                   "speedup_vs_learned_step": t_b / t_p, "prep_s": prep_s,
+                  # the fast filter's ops per visited vector over the kernel time
+                  "frac_per_visited": ALG_OPS_PER_VECTOR * visited / (k_p * 1e-3) / INT32_PEAK,
                   "counts_equal_to_full_sweep": True}
         del sw_p, batch_p
 
@@ -461,7 +504,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload].format(count=len(preps)),
                    "instances": len(preps), "sum_2k": vectors, "cbits": args.cbits,
                    "wg_size": args.wg, "waves_per_simd": waves_used, "records": args.records,
-                   "record_copy_parts": args.parts if args.records == "device" else None,
+                   "record_copy_parts": args.parts if args.records == "copy" else None,
                    "schedule": f"learned: {args.learned_policy}, LPT on MLP-predicted cost"},
         "wpm_total": int(res_b.total),
         "wpm_counts_sha256": __import__("hashlib").sha256(res_b.counts.tobytes()).hexdigest(),

@@ -293,7 +293,7 @@ typedef struct wpm_instance_info {
     int32_t n_filter;     /* ridges in the fast filter group */
     int32_t row_words;    /* words per basis row of the packed table */
     int32_t max_facets;   /* upper bound applied (0 = none) */
-    int32_t n_deferred;   /* critical ridges checked by the verification pass */
+    int32_t n_deferred;   /* critical ridges checked after the resident groups */
     int64_t table_words;  /* size of the packed table in uint32 words */
     double filter_pass;   /* estimated fraction of x passing the filter */
     double full_pass;     /* estimated fraction of x passing every ridge */
@@ -531,7 +531,11 @@ typedef struct wpm_host_instance {
  *   h_counts     [num] receives the exact per-instance counts
  *   h_out        [out_cap] uint32; per instance, in canonical order, each
  *                result as [len, facet masks ascending]; results of one
- *                instance are sorted lexicographically
+ *                instance are sorted lexicographically.  NULL asks only for
+ *                out_words (and h_counts, h_offsets).  A result of instance
+ *                i takes at most 1 + min(M_i, its facet bound) words, so
+ *                out_cap = sum over i of count_i (1 + M_i) always suffices
+ *                and saves the second call
  *   h_offsets    [num + 1] int64: word offset of each instance's results
  *   out_words    receives the words needed (when the record buffer
  *                overflowed: minus the record slots needed)

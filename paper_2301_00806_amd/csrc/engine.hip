@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -330,17 +331,17 @@ int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv,
     if (sum != total) return WPM_EINVAL;  // counts and total disagree: corrupted buffers
     // the records: read in place when they are in host memory, else copied
     const uint64_t *rec = d_surv;
-    std::vector<uint64_t> rec_copy;
+    std::unique_ptr<uint64_t[]> rec_copy;  // uninitialised: the copy fills it
     {
         hipPointerAttribute_t attr;
         const bool host = hipPointerGetAttributes(&attr, d_surv) == hipSuccess &&
                           attr.type == hipMemoryTypeHost;
         (void)hipGetLastError();
         if (!host && slots) {
-            rec_copy.resize(2 * slots);
-            HIP_TRY(hipMemcpyAsync(rec_copy.data(), d_surv, sizeof(uint64_t) * 2 * slots, hipMemcpyDefault, st));
+            rec_copy.reset(new uint64_t[2 * slots]);
+            HIP_TRY(hipMemcpyAsync(rec_copy.get(), d_surv, sizeof(uint64_t) * 2 * slots, hipMemcpyDefault, st));
             HIP_TRY(hipStreamSynchronize(st));
-            rec = rec_copy.data();
+            rec = rec_copy.get();
         }
     }
     // group the records by instance: per-range histograms, then scatter
@@ -373,7 +374,7 @@ int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv,
         if ((uint64_t)c != h_counts[i]) return WPM_EINVAL;
         start[i + 1] = start[i] + c;
     }
-    std::vector<uint64_t> xs((size_t)start[num]);
+    std::unique_ptr<uint64_t[]> xs(new uint64_t[(size_t)std::max<int64_t>(1, start[num])]);
     host_parallel_for(ranges, [&](int64_t r) {
         int64_t *h = hist.data() + (size_t)r * num;
         const uint64_t e = std::min<uint64_t>(slots, (uint64_t)(r + 1) * per);
@@ -382,38 +383,20 @@ int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv,
             if (inst != ~0ull) xs[(size_t)h[inst]++] = rec[2 * q];
         }
     }, 1);
-    // words per instance: one length word plus |K| facets per complex
+    // Per instance: the x values expanded into permuted bit vectors (kept
+    // when the lists are to be written) and the words of its lists, one
+    // length word plus |K| facets per complex.
+    const bool write = h_out != nullptr;
+    std::vector<SortedFacets> sfs(write ? (size_t)num : 0);
+    std::vector<std::vector<uint32_t>> kvs(write ? (size_t)num : 0);
     std::vector<int64_t> iw((size_t)num, 0);
-    host_parallel_for(num, [&](int64_t i) {
-        const int W = (insts[i].M + 31) / 32;
-        int64_t w = 0;
-        uint32_t K[WPM_MAX_M / 32];
-        for (int64_t r = start[i]; r < start[i + 1]; ++r) {
-            for (int q = 0; q < W; ++q) K[q] = insts[i].offset ? insts[i].offset[q] : 0u;
-            for (uint64_t b = xs[(size_t)r]; b; b &= b - 1) {
-                const uint32_t *row = insts[i].basis + (size_t)__builtin_ctzll(b) * W;
-                for (int q = 0; q < W; ++q) K[q] ^= row[q];
-            }
-            w += 1;
-            for (int q = 0; q < W; ++q) w += __builtin_popcount(K[q]);
-        }
-        iw[(size_t)i] = w;
-    });
-    int64_t words = 0;
-    for (int i = 0; i < num; ++i) {
-        h_offsets[i] = words;
-        words += iw[(size_t)i];
-    }
-    h_offsets[num] = words;
-    *out_words = words;
-    if (!h_out || out_cap < words) return WPM_ECAP;
-    // per instance: permuted bit vectors, canonical sort, facet lists
     host_parallel_for(num, [&](int64_t i) {
         const int64_t n_i = start[i + 1] - start[i];
         if (!n_i) return;
-        const SortedFacets sf = sort_facets(insts[i]);
+        SortedFacets sf = sort_facets(insts[i]);
         const int W = sf.W;
         std::vector<uint32_t> kv((size_t)n_i * (size_t)std::max(W, 1));
+        int64_t w = n_i;
         for (int64_t r = 0; r < n_i; ++r) {
             uint32_t *K = kv.data() + (size_t)r * W;
             for (int q = 0; q < W; ++q) K[q] = sf.off[q];
@@ -421,7 +404,30 @@ int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv,
                 const uint32_t *row = sf.basis.data() + (size_t)__builtin_ctzll(b) * W;
                 for (int q = 0; q < W; ++q) K[q] ^= row[q];
             }
+            for (int q = 0; q < W; ++q) w += __builtin_popcount(K[q]);
         }
+        iw[(size_t)i] = w;
+        if (write) {
+            sfs[(size_t)i] = std::move(sf);
+            kvs[(size_t)i] = std::move(kv);
+        }
+    });
+    xs.reset();
+    int64_t words = 0;
+    for (int i = 0; i < num; ++i) {
+        h_offsets[i] = words;
+        words += iw[(size_t)i];
+    }
+    h_offsets[num] = words;
+    *out_words = words;
+    if (!write || out_cap < words) return WPM_ECAP;
+    // per instance: canonical sort of the bit vectors, then the facet lists
+    host_parallel_for(num, [&](int64_t i) {
+        const int64_t n_i = start[i + 1] - start[i];
+        if (!n_i) return;
+        const SortedFacets &sf = sfs[(size_t)i];
+        const int W = sf.W;
+        std::vector<uint32_t> &kv = kvs[(size_t)i];
         std::vector<int64_t> idx((size_t)n_i);
         for (int64_t r = 0; r < n_i; ++r) idx[(size_t)r] = r;
         std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
@@ -439,6 +445,7 @@ int collect(const wpm_host_instance *insts, int32_t num, const uint64_t *d_surv,
                 }
             *len = n;
         }
+        std::vector<uint32_t>().swap(kv);
     }, 1);
     return WPM_OK;
 }

@@ -36,7 +36,7 @@ enum {
     HDR_PROPS = 12,   // word offset of the property section (0: none)
     HDR_NPROPS = 13,  // affine properties besides the facet bound
     HDR_DEFER = 14,   // word offset of the deferred-ridge section (0: none)
-    HDR_NDEFER = 15,  // deferred ridges: checked on survivors by the verification pass
+    HDR_NDEFER = 15,  // deferred ridges: checked after the resident groups
 };
 constexpr uint32_t HDR_FLAG_OFFSET = 1;
 

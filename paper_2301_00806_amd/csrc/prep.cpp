@@ -443,7 +443,8 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
     }
     const int64_t alive_full = count_alive();
     // Resident groups: the filter and the first ridges of the greedy order;
-    // the rest of the critical ridges are deferred to the verification pass.
+    // the rest of the critical ridges are deferred: the sweep checks them on
+    // every vector that passes the resident groups.
     std::vector<int> deferred;
     const size_t resident_rest = (size_t)(max_groups - 1) * 32;
     if (rest.size() > resident_rest) {

@@ -148,7 +148,7 @@ __device__ __forceinline__ const T *opaque(const T *p) {
 }
 
 // Occupancy: the kernel is compiled for WAVES waves per SIMD.  Its state is
-// the two phase-1 chains and loop control; everything a check needs comes
+// the four phase-1 chains and loop control; everything a check needs comes
 // from LDS.
 template <int WAVES>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES)))

@@ -510,6 +510,7 @@ class Sweeper:
         self._times = None
         self._segments = []
         self._seg_bins = []
+        self._staging = None  # pinned copy target of HBM records (reserve_host_staging)
 
     def set_items(self, items: np.ndarray, want_times: bool = False,
                   bin_offsets: Optional[np.ndarray] = None, segments=None,
@@ -717,6 +718,14 @@ class Sweeper:
             res.append(lst)
         return res
 
+    def reserve_host_staging(self) -> None:
+        """Pinned host memory for `cap` records, which collect_raw then uses
+        to bring records from HBM to the host in one DMA copy (a set-up cost,
+        like the record buffer itself)."""
+        if not self.records_on_host and self._staging is None:
+            self._staging = self.torch.empty((max(self.cap, 1), 2), dtype=self.torch.int64,
+                                             pin_memory=True)
+
     def collect_raw(self, stream=None):
         """wpm_collect as flat arrays: (counts, words, offsets[num + 1]).
         Instance i's complexes are words[offsets[i]:offsets[i+1]], each as its
@@ -743,17 +752,32 @@ class Sweeper:
         offs = np.zeros(len(preps) + 1, dtype=np.int64)
         words = ctypes.c_int64(0)
         lib = L.lib()
-        args = (hosts, len(preps), self.surv.data_ptr(), self.cap, self.counts.data_ptr(),
+        torch.cuda.current_stream().wait_stream(stream)
+        surv = self.surv.data_ptr()
+        if not self.records_on_host and self._staging is not None:
+            # records in HBM: one copy into the reserved pinned buffer, which
+            # wpm_collect then reads in place
+            slots = min(int(self.total[1].item()), self.cap)
+            with torch.cuda.stream(stream):
+                self._staging[:slots].copy_(self.surv[:slots], non_blocking=True)
+            stream.synchronize()
+            surv = self._staging.data_ptr()
+        args = (hosts, len(preps), surv, self.cap, self.counts.data_ptr(),
                 self.total.data_ptr(), _ptr(h_counts, L.c_u64p))
-        st = lib.wpm_collect(*args, None, 0, ctypes.byref(words), _ptr(offs, L.c_i64p),
-                             ctypes.c_void_p(stream.cuda_stream))
+        # One call with an output sized by the bound 1 + min(M, facet bound)
+        # words per result; pages past the words written are never touched.
+        cnt = self.counts[:len(preps)].cpu().numpy().astype(np.int64) if len(preps) else np.zeros(0, np.int64)
+        per = np.array([1 + (min(len(p.facets), p.max_facets) if p.max_facets > 0 else len(p.facets))
+                        for p in preps], dtype=np.int64)
+        bound = int((cnt * per).sum()) if len(preps) else 0
+        out = np.empty(max(1, bound), dtype=np.uint32)
+        st = lib.wpm_collect(*args, _ptr(out), bound, ctypes.byref(words),
+                             _ptr(offs, L.c_i64p), ctypes.c_void_p(stream.cuda_stream))
         L.check("wpm_collect", st, (L.WPM_ECAP, L.WPM_OK))
         if words.value < 0:
             raise L.WpmError("wpm_collect (survivor buffer overflow)", L.WPM_ECAP)
-        out = np.zeros(max(1, words.value), dtype=np.uint32)
-        st = lib.wpm_collect(*args, _ptr(out), words.value, ctypes.byref(words),
-                             _ptr(offs, L.c_i64p), ctypes.c_void_p(stream.cuda_stream))
-        L.check("wpm_collect", st)
+        if st == L.WPM_ECAP:
+            raise L.WpmError("wpm_collect (output larger than its bound)", L.WPM_ECAP)
         return h_counts[:len(preps)], out[:words.value], offs
 
 

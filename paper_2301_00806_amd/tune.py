@@ -1,5 +1,6 @@
 """Autotuner for the persistent sweep: lane chunk bits, workgroup size and
-the kernel's register budget (7 or 8 waves per SIMD).
+the kernel's register budget (7 or 8 waves per SIMD); for a pruned sweep
+also the free coordinates a convenient basis keeps (min_free).
 
 It times candidate launch shapes on the batch itself when a sweep of it takes
 well under a second, else on a sample that keeps the batch's mix (every
@@ -111,3 +112,76 @@ def tune(preps: Sequence, cache: Optional[str] = DEFAULT_CACHE, budget_vectors: 
             json.dump(db, f, indent=1)
         os.replace(tmp, cache)
     return dict(entry, cached=False, key=key)
+
+
+MIN_FREES = (16, 18, 20)
+PRUNED_CBITS = (10, 12)
+
+
+def tune_pruned(insts: Sequence, cache: Optional[str] = DEFAULT_CACHE, min_frees=MIN_FREES,
+                cbits=PRUNED_CBITS, wg: int = 256, waves: int = 8, force: bool = False,
+                log=None):
+    """Free coordinates and chunk bits of a pruned sweep, chosen by the
+    time of the whole batch: fewer free coordinates prune more vectors but
+    shorten the lane chunks of each block tuple (one tuple spans 2^min_free
+    indices).  The score is the covered vectors (the plain sweep's 2^k) per
+    second.  Returns (entry, preps prepared with the chosen min_free)."""
+    import torch
+    db = {}
+    if cache and os.path.exists(cache):
+        try:
+            with open(cache) as f:
+                db = json.load(f)
+        except (OSError, ValueError):
+            db = {}
+    prepared = {}
+
+    def prep(mf):
+        if mf not in prepared:
+            prepared[mf] = E.prepare_many(insts, prune=True, min_free=mf)
+        return prepared[mf]
+
+    first = prep(min_frees[len(min_frees) // 2])
+    key = shape_key(E.DeviceBatch(first)) + "/minfree"
+    if key in db and not force:
+        e = db[key]
+        return dict(e, cached=True, key=key), prep(int(e["min_free"]))
+    results, ref = [], None
+    covered = float(sum(1 << p.k for p in first))
+    for mf in min_frees:
+        batch = E.DeviceBatch(prep(mf))
+        sw = E.Sweeper(batch, cap=1 << 26)
+        for cb in cbits:
+            items = E.build_queue(batch.k, cb, wg, cost=np.ones(len(batch.preps), np.float32),
+                                  order=1, blocks=batch.blocks)
+            sw.set_items(items)
+            sw.launch(L.SCHED_DYNAMIC, wg_size=wg, waves=waves)
+            r = sw.result()
+            if ref is None:
+                ref = r.counts.copy()
+            if not np.array_equal(r.counts, ref):
+                raise RuntimeError(f"counts changed with min_free={mf} cbits={cb}")
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sw.launch(L.SCHED_DYNAMIC, wg_size=wg, waves=waves)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            results.append({"min_free": mf, "cbits": cb, "ms": ms, "visited": batch.visited,
+                            "covered_per_s": covered / ms * 1e3})
+            if log:
+                log(f"tune pruned min_free={mf} cbits={cb}: {ms:.2f} ms, visits {batch.visited:.3e} "
+                    f"({covered / ms * 1e3:.3e} covered vectors/s)")
+        del sw, batch
+    best = max(results, key=lambda r: r["covered_per_s"])
+    entry = {"min_free": best["min_free"], "cbits": best["cbits"], "wg": wg, "waves": waves,
+             "results": results, "when": time.time()}
+    if cache:
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        db[key] = entry
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1)
+        os.replace(tmp, cache)
+    return dict(entry, cached=False, key=key), prep(int(best["min_free"]))

@@ -211,7 +211,7 @@ def test_build_queue_groups_and_counts():
 @pytest.mark.parametrize("case", _instances_small(), ids=lambda c: c[0])
 def test_deferred_ridges_keep_table_semantics(case):
     # only the filter group (or two groups) resident: the other critical
-    # ridges are listed for the verification pass
+    # ridges are listed as deferred ridges, checked after the resident groups
     name, n, m, lam, facets = case
     for mg in (1, 2):
         p = E.prepare(n, m, lam=lam, facets=facets, max_groups=mg)

@@ -3,7 +3,7 @@ gfx950 code; no GPU needed).
 
 One kernel serves every instance shape, compiled for 7 and for 8 waves per
 SIMD (at most 72 and 64 VGPRs: VGPRs are allocated in granules of 8 out of
-512 per SIMD lane).  Its only per-lane state is the fast filter's two chains;
+512 per SIMD lane).  Its only per-lane state is the fast filter's four chains;
 a check rebuilds any other word from LDS tables.  So the whole kernel, not
 just its hot loop, must compile without any scratch access: no spill traffic
 reaches memory.  The per-block path -- the basic blocks of the loop holding
