@@ -370,6 +370,37 @@ class DeviceBatch:
         """Vectors a sweep of the batch visits (less than `vectors` when pruned)."""
         return int(sum(p.visited for p in self.preps))
 
+    def class_queue_args(self):
+        """Per launch class, widest first: (class, vectors visited, k with
+        the other classes' instances zeroed, wpm_blocks likewise or None),
+        built once per batch."""
+        if getattr(self, "_cq", None) is None:
+            vis = np.array([float(p.visited) if p.k > 0 else 0.0 for p in self.preps])
+            out = []
+            for code in sorted(np.unique(self.cls), reverse=True):
+                sel = self.cls == code
+                vec = float(vis[sel].sum())
+                if vec == 0.0:
+                    continue
+                k_sel = np.where(sel, self.k, 0).astype(np.int32)
+                blocks = None
+                if self.blocks is not None:
+                    blocks = (L.Blocks * len(self.preps))()
+                    for i in np.flatnonzero(sel):
+                        blocks[i] = self.blocks[i]
+                out.append((int(code), vec, k_sel, blocks))
+            self._cq = out
+        return self._cq
+
+    def class_grid(self, cls: int, wg_size: int) -> int:
+        """persistent_grid of one launch class, cached per workgroup size."""
+        if getattr(self, "_grids", None) is None:
+            self._grids = {}
+        key = (cls, wg_size)
+        if key not in self._grids:
+            self._grids[key] = persistent_grid(self, wg_size, cls)
+        return self._grids[key]
+
 
 def build_queue(k: np.ndarray, cbits: int, lanes: int, cost: Optional[np.ndarray] = None,
                 max_items_per_instance: int = 0, order: int = 0,
@@ -456,19 +487,28 @@ def split_by_class(batch: "DeviceBatch", items: np.ndarray):
 
 
 def class_items(batch: "DeviceBatch", cbits: int, lanes: int, cost: Optional[np.ndarray] = None,
-                order: int = 0, min_items_per_instance: int = 1, max_items_per_instance: int = 0):
-    """Items grouped by launch class (widest first) straight from the
-    builder, with their segments: one launch per class."""
-    items, per = build_queue(batch.k, cbits, lanes, cost=cost, order=order,
-                             min_items_per_instance=min_items_per_instance,
-                             max_items_per_instance=max_items_per_instance,
-                             group=batch.cls, return_counts=True, blocks=batch.blocks)
-    segs, pos = [], 0
-    for code in sorted(np.unique(batch.cls), reverse=True):
-        n = int(per[batch.cls == code].sum())
-        if n:
-            segs.append(Segment(int(code), pos, pos + n))
-            pos += n
+                order: int = 0, min_items_per_instance: int = 1, max_items_per_instance: int = 0,
+                fill: int = 4):
+    """Items grouped by launch class (widest first), with their segments:
+    one launch per class.  A class too small to give its persistent grid
+    `fill` items per workgroup at `cbits` gets shorter lane chunks (down to
+    2^7), so that its launch spreads over the whole device instead of
+    running a few long items on an otherwise idle GPU."""
+    parts, segs, pos = [], [], 0
+    for code, vec, k_sel, blocks in batch.class_queue_args():
+        c = cbits
+        if fill > 0:
+            grid = batch.class_grid(int(code), lanes)
+            while c > 7 and vec / (lanes * float(1 << c)) < fill * grid:
+                c -= 1
+        it = build_queue(k_sel, c, lanes, cost=cost, order=order,
+                         min_items_per_instance=min_items_per_instance,
+                         max_items_per_instance=max_items_per_instance, blocks=blocks)
+        if len(it):
+            parts.append(it)
+            segs.append(Segment(int(code), pos, pos + len(it)))
+            pos += len(it)
+    items = np.concatenate(parts) if parts else np.zeros(0, dtype=ITEM_DTYPE)
     return items, segs
 
 

@@ -92,3 +92,19 @@ def test_pruned_stress_outputs_verified(E):
     plain = E.prepare_many(insts)
     res_q, _ = run(E, plain, cbits=12, want_sets=False)
     assert np.array_equal(res_q.counts, res.counts)
+
+
+def test_pruned_autotuner_keeps_counts(E):
+    # the tuner re-prepares the batch for each min_free and times each chunk
+    # size; every shape must give the oracle's counts
+    from paper_2301_00806_amd import tune as T
+    insts = [i for i in W.batch(E.kdim, count=64) if i.meta["k"] <= 20][:24]
+    _say(f"[gpu] pruned autotuner over {len(insts)} instances")
+    entry, preps = T.tune_pruned(insts, cache=None, min_frees=(8, 10), cbits=(8, 10))
+    assert entry["min_free"] in (8, 10) and entry["cbits"] in (8, 10)
+    assert len(entry["results"]) == 4 and not entry["cached"]
+    assert any(p.blocks is not None and p.blocks.num_blocks > 0 for p in preps)
+    res, sets = run(E, preps, cbits=int(entry["cbits"]), wg_size=256, order=1)
+    want = oracle_sets(preps)
+    assert sets == want
+    assert list(res.counts) == [len(w) for w in want]
