@@ -235,17 +235,6 @@ int kernel_basis(int n, int m, const uint32_t *facets, int32_t M, uint32_t *ridg
 
 namespace {
 
-// Bit-sliced "at least 3 of these words" over the parents of one ridge.
-inline uint64_t at_least3(const uint64_t *w, int cnt) {
-    uint64_t c1 = 0, c2 = 0, c3 = 0;
-    for (int i = 0; i < cnt; ++i) {
-        c3 |= c2 & w[i];
-        c2 |= c1 & w[i];
-        c1 |= w[i];
-    }
-    return c3;
-}
-
 int slot_stride_for(int q) { return q <= 4 ? 4 : 8; }
 
 }  // namespace
@@ -313,7 +302,12 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
     // Sample the vectors the sweep visits (all of them when there are few),
     // bit-sliced: X[t][s] bit b = coefficient t of sample 64 s + b.  A pruned
     // instance visits only the product of its blocks' allowed sets times the
-    // free coordinates, so its samples come from that set.
+    // free coordinates, so its samples come from that set.  The filter's
+    // pass rate is small (about 1e-3), so its last picks are ranked on the
+    // few samples that pass the first ones: large instances, which hold
+    // nearly all of a batch's work, get up to 2^18 samples; the sample count
+    // scales with the instance (1 per 1024 vectors, at least 8192).
+    constexpr double T_MIN = 8192.0, T_MAX = 262144.0;
     int T;
     bool exact = false;
     double visited = std::ldexp(1.0, k);
@@ -321,11 +315,12 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
         visited = std::ldexp(1.0, blocks->free_dims);
         for (int b = 0; b < blocks->num_blocks; ++b) visited *= (double)blocks->count[b];
     }
-    if (visited <= 8192.0) {
+    const double want = std::min(T_MAX, std::max(T_MIN, visited / 1024.0));
+    if (visited <= want) {
         T = (int)visited;
         exact = true;
     } else {
-        T = 8192;
+        T = (int)want & ~63;
     }
     const int TW = (T + 63) / 64;
     std::vector<uint64_t> X((size_t)std::max(k, 1) * TW, 0);
@@ -369,33 +364,59 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
         }
     }
     const uint64_t tail_mask = (T % 64) ? ((1ull << (T % 64)) - 1) : ~0ull;
-    // Parent bits of every critical ridge over the samples -> fail sets.
-    std::vector<uint64_t> fail((size_t)n_crit * TW, 0);
-    std::vector<uint64_t> pw((size_t)maxp_all * TW);
+    // Membership of each facet that is a parent of a critical ridge, over the
+    // samples (computed once per facet), then the fail set of every critical
+    // ridge: at least 3 of its parents in K, i.e. degree 4 or more.
+    std::vector<int32_t> fcol(M, -1);
+    int nf = 0;
     for (int c = 0; c < n_crit; ++c) {
         const int r = crit[c];
-        const int p0 = inc.parent_off[r], p = inc.parent_off[r + 1] - p0;
-        for (int q = 0; q < p; ++q) {
-            const uint64_t fr = frow[inc.parents[p0 + q]];
-            const uint64_t o = offj[inc.parents[p0 + q]] ? ~0ull : 0ull;
-            for (int s = 0; s < TW; ++s) {
-                uint64_t acc = o;
-                for (uint64_t b = fr; b; b &= b - 1) acc ^= X[(size_t)__builtin_ctzll(b) * TW + s];
-                pw[(size_t)q * TW + s] = acc;
-            }
-        }
-        std::vector<uint64_t> col(p);
-        for (int s = 0; s < TW; ++s) {
-            for (int q = 0; q < p; ++q) col[q] = pw[(size_t)q * TW + s];
-            fail[(size_t)c * TW + s] = at_least3(col.data(), p) & (s == TW - 1 ? tail_mask : ~0ull);
+        for (int q = inc.parent_off[r]; q < inc.parent_off[r + 1]; ++q)
+            if (fcol[inc.parents[q]] < 0) fcol[inc.parents[q]] = nf++;
+    }
+    std::vector<uint64_t> cols((size_t)std::max(nf, 1) * TW);
+    for (int j = 0; j < M; ++j) {
+        if (fcol[j] < 0) continue;
+        uint64_t *cj = cols.data() + (size_t)fcol[j] * TW;
+        const uint64_t o = offj[j] ? ~0ull : 0ull;
+        for (int s = 0; s < TW; ++s) cj[s] = o;
+        for (uint64_t b = frow[j]; b; b &= b - 1) {
+            const uint64_t *xt = X.data() + (size_t)__builtin_ctzll(b) * TW;
+            for (int s = 0; s < TW; ++s) cj[s] ^= xt[s];
         }
     }
+    std::vector<uint64_t> fail((size_t)n_crit * TW, 0);
+    {
+        std::vector<const uint64_t *> pc(maxp_all);
+        for (int c = 0; c < n_crit; ++c) {
+            const int r = crit[c];
+            const int p0 = inc.parent_off[r], p = inc.parent_off[r + 1] - p0;
+            for (int q = 0; q < p; ++q) pc[q] = cols.data() + (size_t)fcol[inc.parents[p0 + q]] * TW;
+            uint64_t *fc = fail.data() + (size_t)c * TW;
+            for (int s = 0; s < TW; ++s) {
+                uint64_t c1 = 0, c2 = 0, c3 = 0;
+                for (int q = 0; q < p; ++q) {
+                    const uint64_t w = pc[q][s];
+                    c3 |= c2 & w;
+                    c2 |= c1 & w;
+                    c1 |= w;
+                }
+                fc[s] = c3;
+            }
+            fc[TW - 1] &= tail_mask;
+        }
+    }
+    std::vector<uint64_t>().swap(cols);
+    std::vector<uint64_t>().swap(X);
     // Greedy ordering: repeatedly take the ridge that rejects the most samples
     // still alive; when none rejects any, order the rest by their own
     // rejection counts.  The filter group takes the first (at most) 32 ridges
-    // with <= 5 parents (4 slot words); any order is exact.
+    // with <= 5 parents (4 slot words); any order is exact.  Only the sample
+    // words that still hold an alive sample are scanned.
     std::vector<uint64_t> alive(TW, ~0ull);
     alive[TW - 1] = tail_mask;
+    std::vector<int32_t> aw(TW);
+    for (int w = 0; w < TW; ++w) aw[w] = w;
     std::vector<int> solo(n_crit, 0);
     for (int c = 0; c < n_crit; ++c) {
         int s = 0;
@@ -412,7 +433,8 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
             if (need_small && pr > 5) continue;
             if (pr - 1 > WPM_MAX_SLOTS) continue;  // too many parents to be resident
             int g = 0;
-            for (int w = 0; w < TW; ++w) g += __builtin_popcountll(fail[(size_t)c * TW + w] & alive[w]);
+            const uint64_t *fc = fail.data() + (size_t)c * TW;
+            for (int w : aw) g += __builtin_popcountll(fc[w] & alive[w]);
             if (g > best_gain || (g == best_gain && g == 0 && solo[c] > solo[best])) {
                 best = c;
                 best_gain = g;
@@ -420,13 +442,19 @@ int pack_instance(int n, int m, const uint32_t *facets, int32_t M, const uint32_
         }
         if (best >= 0) {
             used[best] = 1;
-            for (int w = 0; w < TW; ++w) alive[w] &= ~fail[(size_t)best * TW + w];
+            const uint64_t *fb = fail.data() + (size_t)best * TW;
+            size_t keep = 0;
+            for (int w : aw) {
+                alive[w] &= ~fb[w];
+                if (alive[w]) aw[keep++] = w;
+            }
+            aw.resize(keep);
         }
         return best;
     };
     auto count_alive = [&]() {
         int64_t s = 0;
-        for (int w = 0; w < TW; ++w) s += __builtin_popcountll(alive[w]);
+        for (int w : aw) s += __builtin_popcountll(alive[w]);
         return s;
     };
     std::vector<int> filt, rest;
