@@ -402,14 +402,36 @@ class DeviceBatch:
         return self._grids[key]
 
 
+class PinnedItems(np.ndarray):
+    """Items in pinned host memory (`_tensor` owns it), which set_items
+    copies to the device asynchronously."""
+
+    def __array_finalize__(self, obj):
+        self._tensor = getattr(obj, "_tensor", None)
+
+
+def pinned_items(n: int) -> np.ndarray:
+    """An item array of length n in pinned host memory (plain memory when
+    no GPU is present)."""
+    import torch
+    if not torch.cuda.is_available():
+        return np.zeros(n, dtype=ITEM_DTYPE)
+    t = torch.empty(max(1, n) * ITEM_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True)
+    arr = t.numpy().view(ITEM_DTYPE)[:n].view(PinnedItems)
+    arr._tensor = t
+    return arr
+
+
 def build_queue(k: np.ndarray, cbits: int, lanes: int, cost: Optional[np.ndarray] = None,
                 max_items_per_instance: int = 0, order: int = 0,
                 min_items_per_instance: int = 1, group: Optional[np.ndarray] = None,
-                return_counts: bool = False, blocks=None):
+                return_counts: bool = False, blocks=None, out=None, count_only: bool = False):
     """Items of a batch (wpm_build_queue; wpm_build_pruned_queue when
     `blocks`, a ctypes array of wpm_blocks, is given).  With `group`, items
     come out group by group in decreasing group key; return_counts adds the
-    items per instance."""
+    items per instance.  `out`, a callable taking the item count, supplies
+    the array to fill (default: a new array); count_only returns the item
+    count alone."""
     lib = L.lib()
     ka = np.ascontiguousarray(k, dtype=np.int32)
     ca = None if cost is None else np.ascontiguousarray(cost, dtype=np.float32)
@@ -427,11 +449,14 @@ def build_queue(k: np.ndarray, cbits: int, lanes: int, cost: Optional[np.ndarray
     st = call(first, cp, gp, len(ka), cbits, lanes, min_items_per_instance,
               max_items_per_instance, order, None, 0, ctypes.byref(n), None)
     L.check(name, st, (L.WPM_ECAP, L.WPM_OK))
-    arr = np.zeros(max(1, n.value), dtype=ITEM_DTYPE)
-    st = call(first, cp, gp, len(ka), cbits, lanes, min_items_per_instance,
-              max_items_per_instance, order, arr.ctypes.data_as(ctypes.POINTER(L.Item)), n.value,
-              ctypes.byref(n), _ptr(per, L.c_i64p))
-    L.check(name, st)
+    if count_only:
+        return n.value
+    arr = np.zeros(max(1, n.value), dtype=ITEM_DTYPE) if out is None else out(n.value)
+    if n.value:
+        st = call(first, cp, gp, len(ka), cbits, lanes, min_items_per_instance,
+                  max_items_per_instance, order, arr.ctypes.data_as(ctypes.POINTER(L.Item)), n.value,
+                  ctypes.byref(n), _ptr(per, L.c_i64p))
+        L.check(name, st)
     arr = arr[:n.value]
     return (arr, per[:len(ka)]) if return_counts else arr
 
@@ -494,21 +519,26 @@ def class_items(batch: "DeviceBatch", cbits: int, lanes: int, cost: Optional[np.
     `fill` items per workgroup at `cbits` gets shorter lane chunks (down to
     2^7), so that its launch spreads over the whole device instead of
     running a few long items on an otherwise idle GPU."""
-    parts, segs, pos = [], [], 0
+    plan = []
     for code, vec, k_sel, blocks in batch.class_queue_args():
         c = cbits
         if fill > 0:
             grid = batch.class_grid(int(code), lanes)
             while c > 7 and vec / (lanes * float(1 << c)) < fill * grid:
                 c -= 1
-        it = build_queue(k_sel, c, lanes, cost=cost, order=order,
-                         min_items_per_instance=min_items_per_instance,
-                         max_items_per_instance=max_items_per_instance, blocks=blocks)
-        if len(it):
-            parts.append(it)
-            segs.append(Segment(int(code), pos, pos + len(it)))
-            pos += len(it)
-    items = np.concatenate(parts) if parts else np.zeros(0, dtype=ITEM_DTYPE)
+        plan.append((code, c, k_sel, blocks))
+    kw = dict(cost=cost, order=order, min_items_per_instance=min_items_per_instance,
+              max_items_per_instance=max_items_per_instance)
+    # count each class's items, then build them all into one pinned array
+    counts = [build_queue(k_sel, c, lanes, blocks=blocks, count_only=True, **kw)
+              for code, c, k_sel, blocks in plan]
+    items = pinned_items(int(sum(counts)))
+    segs, pos = [], 0
+    for (code, c, k_sel, blocks), n in zip(plan, counts):
+        if n:
+            build_queue(k_sel, c, lanes, blocks=blocks, out=lambda m, a=pos: items[a:a + m], **kw)
+            segs.append(Segment(int(code), pos, pos + n))
+            pos += n
     return items, segs
 
 
@@ -565,12 +595,22 @@ class Sweeper:
                 segments = [Segment(None, 0, len(items), bin_offsets)]
             else:
                 items, segments = split_by_class(self.batch, np.ascontiguousarray(items))
-        self._items_host = np.ascontiguousarray(items)
+        pinned = getattr(items, "_tensor", None)
+        if pinned is not None and (items.ctypes.data != pinned.data_ptr() or not items.flags["C_CONTIGUOUS"]):
+            pinned = None   # a view into the pinned array: copied the plain way
+        self._items_host = items if pinned is not None else np.ascontiguousarray(items)
         self._segments = segments
         self._seg_bins = [None if sg.bins is None else torch.from_numpy(
             np.ascontiguousarray(sg.bins, np.int64)).to(self.device) for sg in segments]
-        raw = self._items_host.view(np.int64).reshape(-1) if len(items) else np.zeros(2, np.int64)
-        self._items_dev = torch.from_numpy(raw.copy()).to(self.device)
+        if pinned is not None and len(items):
+            # pinned host items (class_items builds them there): an
+            # asynchronous copy on the current stream; the pinned block is
+            # not reused before the copy has run
+            self._items_dev = torch.empty(2 * len(items), dtype=torch.int64, device=self.device)
+            self._items_dev.copy_(pinned[:16 * len(items)].view(torch.int64), non_blocking=True)
+        else:
+            raw = self._items_host.view(np.int64).reshape(-1) if len(items) else np.zeros(2, np.int64)
+            self._items_dev = torch.from_numpy(raw.copy()).to(self.device)
         self._times = (torch.zeros((max(1, len(items)), 2), dtype=torch.int64, device=self.device)
                        if want_times else None)
 
