@@ -394,6 +394,8 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                 // the slots).  Steps that would overflow the list are only
                 // marked in a scalar mask and rechecked below.
                 constexpr int NC = PH1_CHAINS, SL = 64 / NC;
+                // the chain offsets' Gray bits lie in 3-5: one row of table 1
+                static_assert(SL % 8 == 0 && NC * SL == 64, "chain starts with Gray bits 3-5 only");
                 uint64_t redo = 0;
                 uint32_t c[NC][4];
 #pragma unroll
@@ -402,12 +404,11 @@ void sweep_kernel(const uint32_t *__restrict__ tables, const int64_t *__restrict
                     if (j == 0) {
                         c[0][0] = s0; c[0][1] = s1; c[0][2] = s2; c[0][3] = s3;
                     } else {
-                        const uint4 o0 = *(const uint4 *)(lds_T + (g & 7u) * RS);
-                        const uint4 o1 = *(const uint4 *)(lds_T + (8u + (g >> 3)) * RS);
-                        c[j][0] = xor3(s0, o0.x, o1.x);
-                        c[j][1] = xor3(s1, o0.y, o1.y);
-                        c[j][2] = xor3(s2, o0.z, o1.z);
-                        c[j][3] = xor3(s3, o0.w, o1.w);
+                        const uint4 o = *(const uint4 *)(lds_T + (8u + (g >> 3)) * RS);
+                        c[j][0] = s0 ^ o.x;
+                        c[j][1] = s1 ^ o.y;
+                        c[j][2] = s2 ^ o.z;
+                        c[j][3] = s3 ^ o.w;
                     }
                 }
 #pragma unroll
