@@ -196,6 +196,22 @@ def test_launch_class_split_keeps_every_item():
         assert set(FakeBatch.cls[out[s.start:s.end]["instance"]]) == {s.cls}
 
 
+def test_build_queue_count_only_and_caller_array():
+    # the per-class plans count each class's items first and then fill
+    # slices of one (pinned) array: both paths give the plain queue
+    k = np.array([12, 0, 9, 15, 7], dtype=np.int32)
+    cost = np.array([1, 2, 3, 0.5, 1], np.float32)
+    ref = E.build_queue(k, 9, 64, cost=cost, order=1)
+    assert E.build_queue(k, 9, 64, cost=cost, order=1, count_only=True) == len(ref)
+    buf = np.zeros(len(ref) + 5, dtype=E.ITEM_DTYPE)
+    got = E.build_queue(k, 9, 64, cost=cost, order=1, out=lambda n: buf[3:3 + n])
+    assert np.array_equal(got, ref) and np.array_equal(buf[3:3 + len(ref)], ref)
+    raw = buf.view(np.uint64)
+    assert not raw[:6].any() and not raw[2 * (3 + len(ref)):].any()   # untouched outside the slice
+    assert E.build_queue(np.zeros(3, np.int32), 9, 64, count_only=True) == 0
+    assert len(E.build_queue(np.zeros(3, np.int32), 9, 64, out=lambda n: buf[:n])) == 0
+
+
 def test_build_queue_groups_and_counts():
     k = np.array([9, 12, 16, 8, 0, 20], dtype=np.int32)
     grp = np.array([1, 3, 1, 2, 3, 3], dtype=np.int32)
