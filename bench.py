@@ -310,8 +310,9 @@ def main():
     step_med, kern_med = timed_plan.medians
 
     # ---- roofline launch: the learned plan once more, every class as a
-    # single dispatch (the timed steps split the largest class into parts so
-    # that record copies overlap it); its events time the dominant kernel
+    # single dispatch with HIP events around each (with --records copy the
+    # timed steps split the largest class into parts); its events time the
+    # dominant kernel
     plan = plan_learned()
     sw.set_items(plan.items, segments=plan.segments)
     sw.launch(plan.mode, wg_size=args.wg, stream=stream, seg_events=True, waves=args.waves)
