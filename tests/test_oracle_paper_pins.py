@@ -38,7 +38,7 @@ def test_oracle_orbit_counts_match_table1(n):
     assert len(OI.orbit_representatives(n)) == t["idcm_orbits"][t["n"].index(n)]
 
 
-@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("n", list(range(2, 12)))
 def test_oracle_max_kernel_dimension_over_orbits_matches_table1(n):
     t = _table1()
     m = n + 4
