@@ -25,7 +25,7 @@ from . import engine as E
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "wpm_tune.json")
 CBITS = (10, 11, 12, 13, 14)
-WGS = (256,)
+WGS = (256, 512)
 WAVES = (7, 8)
 
 
