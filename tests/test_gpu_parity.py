@@ -97,6 +97,24 @@ def test_batch_mixed(E):
     assert res.total == sum(len(w) for w in want)
 
 
+@pytest.mark.parametrize("waves", [7, 8])
+def test_512_thread_workgroups_match_oracle(E, waves):
+    # eight waves share one workgroup's staged tables (an autotuner option)
+    insts = [i for i in W.batch(E.kdim, count=64) if i.meta["k"] <= 20][:24]
+    preps = E.prepare_many(insts)
+    batch = E.DeviceBatch(preps)
+    sw = E.Sweeper(batch, cap=1 << 20)
+    items = E.build_queue(batch.k, 10, 512, cost=np.ones(len(preps), np.float32), order=1)
+    assert items["lanes"].max() == 512
+    sw.set_items(items)
+    _say(f"[gpu] 512-thread workgroups, {waves} waves per SIMD, {len(items)} items")
+    sw.launch(2, wg_size=512, waves=waves)
+    res = sw.result()
+    want = oracle_sets(preps)
+    assert sw.collect() == want
+    assert list(res.counts) == [len(w) for w in want]
+
+
 def test_schedule_invariance(E):
     insts = W.batch(E.kdim, count=40)
     preps = E.prepare_many(insts)
