@@ -435,26 +435,28 @@ def main():
                   "counts_equal_to_full_sweep": True}
         del sw_p, batch_p
 
-    # model error on the fresh instances: measured per-instance time vs prediction
-    _, Tte, _ = S.measure_labels(preps, cbits=args.cbits, wg=args.wg, repeats=1) if not args.only_learned \
-        else (None, model.predict(feats), None)
-    pred = model.predict(feats)
-    ok = np.isfinite(Tte[:, 0])
-    err = pred[ok, 0] - Tte[ok, 0]
-    base = np.median(Ttr[okt, 0]) - Tte[ok, 0]     # "cost proportional to 2^k": constant ns/vector
-    # the large instances: those holding 90% of the vectors
-    vec_ok = np.array([float(1 << p.k) for p in preps])[ok]
-    big = np.argsort(-vec_ok)
-    big = big[:int(np.searchsorted(np.cumsum(vec_ok[big]) / vec_ok.sum(), 0.9)) + 1]
-    model_err = {"log_rmse": float(np.sqrt(np.mean(err ** 2))),
-                 "mape": float(np.mean(np.abs(np.expm1(err)))),
-                 "log_rmse_pow2_heuristic": float(np.sqrt(np.mean(base ** 2))),
-                 "mape_pow2_heuristic": float(np.mean(np.abs(np.expm1(base)))),
-                 "large_instances": int(len(big)),
-                 "log_rmse_large": float(np.sqrt(np.mean(err[big] ** 2))),
-                 "log_rmse_pow2_heuristic_large": float(np.sqrt(np.mean(base[big] ** 2))),
-                 "train_instances": len(Xtr), "train_loss": train_loss}
-    log(f"model error on fresh instances: {model_err}")
+    # model error on the fresh instances: measured per-instance time vs
+    # prediction (skipped with --only-learned, which measures no labels)
+    model_err = None
+    if not args.only_learned:
+        _, Tte, _ = S.measure_labels(preps, cbits=args.cbits, wg=args.wg, repeats=1)
+        pred = model.predict(feats)
+        ok = np.isfinite(Tte[:, 0])
+        err = pred[ok, 0] - Tte[ok, 0]
+        base = np.median(Ttr[okt, 0]) - Tte[ok, 0]     # "cost proportional to 2^k": constant ns/vector
+        # the large instances: those holding 90% of the vectors
+        vec_ok = np.array([float(1 << p.k) for p in preps])[ok]
+        big = np.argsort(-vec_ok)
+        big = big[:int(np.searchsorted(np.cumsum(vec_ok[big]) / vec_ok.sum(), 0.9)) + 1]
+        model_err = {"log_rmse": float(np.sqrt(np.mean(err ** 2))),
+                     "mape": float(np.mean(np.abs(np.expm1(err)))),
+                     "log_rmse_pow2_heuristic": float(np.sqrt(np.mean(base ** 2))),
+                     "mape_pow2_heuristic": float(np.mean(np.abs(np.expm1(base)))),
+                     "large_instances": int(len(big)),
+                     "log_rmse_large": float(np.sqrt(np.mean(err[big] ** 2))),
+                     "log_rmse_pow2_heuristic_large": float(np.sqrt(np.mean(base[big] ** 2))),
+                     "train_instances": len(Xtr), "train_loss": train_loss}
+        log(f"model error on fresh instances: {model_err}")
 
     if args.copy_calibration:
         a = torch.empty(1 << 26, dtype=torch.int32, device="cuda")
@@ -471,6 +473,12 @@ def main():
     plain_per_vec = plain_ops / cls_vec[dom]
     effective = plain_ops / (dom_ms * 1e-3) / 1e12
     probe = E.valu_probe(0, 4)
+    # the fast step's instruction-mix ceiling: per vector 4.5 two-source ops
+    # (4 XORs, a quarter of a minimum and of a compare) and 2.25 three-source
+    # ops (2 logic ops, a quarter of a 3-input minimum) at the probe's rates
+    probe3 = E.valu_probe(1, 8)
+    probe2 = E.valu_probe(0, 8)
+    mix_ceiling = ALG_OPS_PER_VECTOR / (4.5 / probe2 + 2.25 / probe3)
     counters = None
     cpath = os.path.join(ROOT, "profiles", "sweep_counters.json")
     if os.path.exists(cpath):
@@ -532,6 +540,8 @@ def main():
                              "at the plain per-ridge AND+popcount check of the same launch (saved work, "
                              "not skipped work: every count equals the oracle's)",
                      "measured_int32_xor_peak": probe / 1e12,
+                     "mix_ceiling": mix_ceiling / 1e12,
+                     "mix_ceiling_frac": mix_ceiling / INT32_PEAK,
                      "executed_frac": None if counters is None else
                      counters["executed_lane_ops_per_s"] / INT32_PEAK,
                      "valu_busy": None if counters is None else counters["valu_busy"]},
