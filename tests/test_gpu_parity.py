@@ -182,6 +182,23 @@ def test_records_in_pinned_host_memory(E):
     assert len(out[1][1]) == int(out[1][0].sum())
 
 
+def test_collect_through_pinned_staging(E):
+    # records in HBM, copied by collect into the reserved pinned buffer and
+    # read there in place: the oracle's sets, the same as without staging
+    insts = [i for i in W.batch(E.kdim, count=96, start=7000) if i.meta["k"] <= 22][:24]
+    preps = E.prepare_many(insts)
+    batch = E.DeviceBatch(preps)
+    sw = E.Sweeper(batch, cap=1 << 22)
+    sw.set_items(E.build_queue(batch.k, 10, 256))
+    sw.launch(2, wg_size=256)
+    plain = sw.collect()
+    sw.reserve_host_staging()
+    assert sw._staging is not None and sw._staging.is_pinned()
+    _say(f"[gpu] collect through pinned staging: {len(preps)} instances")
+    staged = sw.collect()
+    assert staged == plain == oracle_sets(preps)
+
+
 def test_capacity_overflow_keeps_counts_exact(E):
     from paper_2301_00806_amd import _lib as L
     f = W.fano()
